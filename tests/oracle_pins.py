@@ -1,0 +1,287 @@
+"""Pins that tie the FP64 oracle to facts fixed by the mathematics, not to itself.
+
+Each pin takes an ``oracle.Oracle`` and raises AssertionError when the oracle
+disagrees with:
+  * an independent formulation (the factorised matrix form F0 X F1^T of
+    Eq. (3)-(4), built with numpy; numpy.fft.fft2 on each window),
+  * exact Gaussian-integer brute force for n_i <= 4 (all twiddles are
+    powers of -i there, so every sum is exact),
+  * closed forms (impulse, constant, on-bin exponential and cosine),
+  * invariants (Parseval per window, the shift theorem between neighbouring
+    windows that recursive sliding DFTs are built on (Sec. 2), linearity),
+  * the adjoint identities (dot-product test, exact central differences of a
+    quadratic loss).
+
+``ALL_PINS`` lists them so the mutation test can run every pin against
+deliberately broken builds of the oracle.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import workloads
+
+
+def _dft_matrix(n: int) -> np.ndarray:
+    k = np.arange(n)
+    return np.exp(-2j * np.pi * np.outer(k, k) / n)
+
+
+def _rel(a, b) -> float:
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def pin_matrix_form(orc):
+    """y_w = F_n0 X_w F_n1^T for every window (factorisation, Eq. (3)-(4))."""
+    rng = np.random.default_rng(11)
+    for (N0, N1, n0, n1) in [(7, 9, 4, 8), (9, 6, 8, 2), (5, 11, 1, 4), (6, 6, 2, 2), (8, 5, 8, 1)]:
+        x = rng.standard_normal((N0, N1)) + 1j * rng.standard_normal((N0, N1))
+        y = orc.swdft2d(x, n0, n1)
+        F0, F1 = _dft_matrix(n0), _dft_matrix(n1)
+        for q0 in range(N0 - n0 + 1):
+            for q1 in range(N1 - n1 + 1):
+                ref = F0 @ x[q0:q0 + n0, q1:q1 + n1] @ F1.T
+                assert _rel(y[q0, q1], ref) < 1e-13, (N0, N1, n0, n1, q0, q1)
+
+
+def pin_fft2(orc):
+    """Each window equals numpy.fft.fft2 of that window (real and complex x)."""
+    rng = np.random.default_rng(12)
+    for (N0, N1, n0, n1) in [(20, 17, 8, 4), (16, 16, 16, 16), (12, 40, 4, 32)]:
+        for cplx in (False, True):
+            x = rng.standard_normal((N0, N1))
+            if cplx:
+                x = x + 1j * rng.standard_normal((N0, N1))
+            y = orc.swdft2d(x, n0, n1)
+            P0, P1 = N0 - n0 + 1, N1 - n1 + 1
+            win = np.lib.stride_tricks.sliding_window_view(x, (n0, n1))
+            ref = np.fft.fft2(win, axes=(-2, -1))
+            assert y.shape == (P0, P1, n0, n1)
+            assert _rel(y, ref) < 1e-13, (N0, N1, n0, n1, cplx)
+
+
+def pin_whole_array(orc):
+    """N = n: one window, the textbook 2D DFT of the whole array."""
+    rng = np.random.default_rng(13)
+    x = rng.standard_normal((8, 32))
+    y = orc.swdft2d(x, 8, 32)
+    assert y.shape == (1, 1, 8, 32)
+    assert _rel(y[0, 0], np.fft.fft2(x)) < 1e-13
+
+
+def pin_exact_small(orc):
+    """Gaussian-integer brute force, exact, on the 2 x 5 array with 2 x 4
+    windows of the worked example of Fig. 3 and a few more tiny shapes.
+
+    For n <= 4 the twiddles are exactly (-i)^(4m/n), so integer inputs give
+    integer outputs and the oracle must match them bit for bit.
+    """
+    rng = np.random.default_rng(14)
+    for (N0, N1, n0, n1) in [(2, 5, 2, 4), (4, 4, 4, 4), (3, 6, 1, 2), (5, 3, 4, 1)]:
+        xr = rng.integers(-9, 10, size=(N0, N1))
+        xi = rng.integers(-9, 10, size=(N0, N1))
+        x = xr + 1j * xi
+        y = orc.swdft2d(x.astype(np.complex128), n0, n1)
+        for q0 in range(N0 - n0 + 1):
+            for q1 in range(N1 - n1 + 1):
+                for k0 in range(n0):
+                    for k1 in range(n1):
+                        acc_r = 0
+                        acc_i = 0
+                        for j0 in range(n0):
+                            for j1 in range(n1):
+                                # exponent of -i: quarter turns of W0^(j0 k0) W1^(j1 k1)
+                                e = ((4 // n0) * j0 * k0 if n0 > 1 else 0) + \
+                                    ((4 // n1) * j1 * k1 if n1 > 1 else 0)
+                                a, b = int(xr[q0 + j0, q1 + j1]), int(xi[q0 + j0, q1 + j1])
+                                for _ in range(e % 4):  # multiply by -i
+                                    a, b = b, -a
+                                acc_r += a
+                                acc_i += b
+                        got = y[q0, q1, k0, k1]
+                        assert got.real == acc_r and got.imag == acc_i, \
+                            (N0, N1, n0, n1, q0, q1, k0, k1, got, acc_r, acc_i)
+
+
+def pin_impulse(orc):
+    """x = delta at (r, c): windows that contain it give the unit-modulus
+    phase exp(-2 pi i ((r-q0) k0/n0 + (c-q1) k1/n1)), other windows give 0."""
+    N0, N1, n0, n1 = 12, 14, 4, 8
+    r, c = 5, 9
+    x = np.zeros((N0, N1))
+    x[r, c] = 1.0
+    y = orc.swdft2d(x, n0, n1)
+    k0 = np.arange(n0)[:, None]
+    k1 = np.arange(n1)[None, :]
+    for q0 in range(N0 - n0 + 1):
+        for q1 in range(N1 - n1 + 1):
+            inside = (q0 <= r < q0 + n0) and (q1 <= c < q1 + n1)
+            if inside:
+                ref = np.exp(-2j * np.pi * ((r - q0) * k0 / n0 + (c - q1) * k1 / n1))
+                assert np.max(np.abs(y[q0, q1] - ref)) < 1e-14
+                assert np.allclose(np.abs(y[q0, q1]), 1.0, atol=1e-14)
+            else:
+                assert np.all(y[q0, q1] == 0)
+
+
+def pin_constant(orc):
+    """x = C everywhere: a = C n0 n1 at k = (0,0) and exactly 0 elsewhere for
+    n_i <= 4 (exact twiddles), <= 1e-13 relative for larger windows."""
+    for (n0, n1, exact) in [(4, 2, True), (16, 8, False)]:
+        C = 3.25
+        x = np.full((n0 + 5, n1 + 3), C)
+        y = orc.swdft2d(x, n0, n1)
+        expect = np.zeros((n0, n1), complex)
+        expect[0, 0] = C * n0 * n1
+        for q0 in range(y.shape[0]):
+            for q1 in range(y.shape[1]):
+                if exact:
+                    assert np.array_equal(y[q0, q1], expect)
+                else:
+                    assert np.max(np.abs(y[q0, q1] - expect)) < 1e-13 * C * n0 * n1
+
+
+def pin_onbin_exponential(orc):
+    """x[r][c] = exp(2 pi i (f0 r/n0 + f1 c/n1)): a single bin k = (f0, f1)
+    holding n0 n1 exp(2 pi i (f0 q0/n0 + f1 q1/n1)); every other bin is 0."""
+    N0, N1, n0, n1 = 19, 23, 8, 16
+    f0, f1 = 3, 11
+    r = np.arange(N0)[:, None]
+    c = np.arange(N1)[None, :]
+    x = np.exp(2j * np.pi * (f0 * r / n0 + f1 * c / n1))
+    y = orc.swdft2d(x, n0, n1)
+    q0 = np.arange(N0 - n0 + 1)[:, None]
+    q1 = np.arange(N1 - n1 + 1)[None, :]
+    peak = n0 * n1 * np.exp(2j * np.pi * (f0 * q0 / n0 + f1 * q1 / n1))
+    assert np.max(np.abs(y[:, :, f0, f1] - peak)) < 1e-11
+    rest = y.copy()
+    rest[:, :, f0, f1] = 0
+    assert np.max(np.abs(rest)) < 1e-11
+
+
+def pin_onbin_cosine(orc):
+    """Real cosine 5 cos(2 pi (f0 r/N0 + f1 c/N1) + phi) with on-bin
+    frequencies (as in the planted workload): two bins of half amplitude,
+    k = (k0, k1) and its mirror (-k0, -k1), each of magnitude 5 n0 n1 / 2."""
+    N0, N1, n0, n1 = 64, 48, 16, 8
+    k0, k1, ph = 3, 2, 0.7
+    f0, f1 = k0 * N0 // n0, k1 * N1 // n1
+    r = np.arange(N0)[:, None]
+    c = np.arange(N1)[None, :]
+    x = 5.0 * np.cos(2 * np.pi * (f0 * r / N0 + f1 * c / N1) + ph)
+    y = orc.swdft2d(x, n0, n1, windows=workloads.window_sample(N0 - n0 + 1, N1 - n1 + 1, 40, 3))
+    mag = np.abs(y)
+    assert np.allclose(mag[:, k0, k1], 5 * n0 * n1 / 2, rtol=1e-12)
+    assert np.allclose(mag[:, (-k0) % n0, (-k1) % n1], 5 * n0 * n1 / 2, rtol=1e-12)
+    mag[:, k0, k1] = 0
+    mag[:, (-k0) % n0, (-k1) % n1] = 0
+    assert np.max(mag) < 1e-10
+
+
+def pin_parseval(orc):
+    """Per window: sum_k |a_k|^2 = n0 n1 sum_j |x_j|^2; with the orthonormal
+    scale of Eq. (2) the two sides are equal."""
+    rng = np.random.default_rng(15)
+    N0, N1, n0, n1 = 21, 18, 8, 4
+    x = rng.standard_normal((N0, N1)) + 1j * rng.standard_normal((N0, N1))
+    win = np.lib.stride_tricks.sliding_window_view(x, (n0, n1))
+    energy = np.sum(np.abs(win) ** 2, axis=(-2, -1))
+    y = orc.swdft2d(x, n0, n1)
+    assert np.allclose(np.sum(np.abs(y) ** 2, axis=(-2, -1)), n0 * n1 * energy, rtol=1e-12)
+    yo = orc.swdft2d(x, n0, n1, norm="ortho")
+    assert np.allclose(np.sum(np.abs(yo) ** 2, axis=(-2, -1)), energy, rtol=1e-12)
+    # n0 n1 = 32 is not a square, so compare the scale itself
+    assert np.allclose(y, yo * np.sqrt(n0 * n1), rtol=1e-13, atol=1e-13)
+
+
+def pin_shift_theorem(orc):
+    """Neighbouring windows: sliding one column right replaces column q1 by
+    column q1+n1 (Fig. 3) and rotates by W1^{-k1}:
+        a[q0][q1+1][k] = W1^{-k1} (a[q0][q1][k] + sum_j0 W0^{j0 k0}
+                         (x[q0+j0][q1+n1] - x[q0+j0][q1]))
+    and likewise for a step down one row."""
+    rng = np.random.default_rng(16)
+    N0, N1, n0, n1 = 13, 15, 4, 8
+    x = rng.standard_normal((N0, N1)) + 1j * rng.standard_normal((N0, N1))
+    y = orc.swdft2d(x, n0, n1)
+    F0, F1 = _dft_matrix(n0), _dft_matrix(n1)
+    k0 = np.arange(n0)[:, None]
+    k1 = np.arange(n1)[None, :]
+    rot1 = np.exp(2j * np.pi * k1 / n1)
+    rot0 = np.exp(2j * np.pi * k0 / n0)
+    for q0 in range(N0 - n0 + 1):
+        for q1 in range(N1 - n1):
+            diff = F0 @ (x[q0:q0 + n0, q1 + n1] - x[q0:q0 + n0, q1])
+            pred = rot1 * (y[q0, q1] + diff[:, None])
+            assert np.max(np.abs(y[q0, q1 + 1] - pred)) < 1e-11
+    for q0 in range(N0 - n0):
+        for q1 in range(N1 - n1 + 1):
+            diff = F1 @ (x[q0 + n0, q1:q1 + n1] - x[q0, q1:q1 + n1])
+            pred = rot0 * (y[q0, q1] + diff[None, :])
+            assert np.max(np.abs(y[q0 + 1, q1] - pred)) < 1e-11
+
+
+def pin_linearity_and_sampling(orc):
+    """Linearity in x; sampled windows equal the same entries of the full output."""
+    rng = np.random.default_rng(17)
+    N0, N1, n0, n1 = 17, 20, 8, 8
+    a = rng.standard_normal((N0, N1))
+    b = rng.standard_normal((N0, N1)) + 1j * rng.standard_normal((N0, N1))
+    ya, yb = orc.swdft2d(a, n0, n1), orc.swdft2d(b, n0, n1)
+    yab = orc.swdft2d(2.5 * a - 1.5j * b, n0, n1)
+    assert _rel(yab, 2.5 * ya - 1.5j * yb) < 1e-13
+    q0, q1 = workloads.window_sample(N0 - n0 + 1, N1 - n1 + 1, 25, 5)
+    ys = orc.swdft2d(b, n0, n1, windows=(q0, q1))
+    assert np.array_equal(ys, yb[q0, q1])
+
+
+def pin_adjoint_dot(orc):
+    """<M x, g> = <x, M^H g> for random complex x, g (several shapes)."""
+    rng = np.random.default_rng(18)
+    for (N0, N1, n0, n1) in [(11, 13, 4, 8), (9, 9, 8, 2), (6, 10, 1, 4)]:
+        x = rng.standard_normal((N0, N1)) + 1j * rng.standard_normal((N0, N1))
+        g = rng.standard_normal((N0 - n0 + 1, N1 - n1 + 1, n0, n1)) + \
+            1j * rng.standard_normal((N0 - n0 + 1, N1 - n1 + 1, n0, n1))
+        lhs = np.vdot(g, orc.swdft2d(x, n0, n1))
+        rhs = np.vdot(orc.swdft2d_adjoint(g, N0, N1), x)
+        assert abs(lhs - rhs) < 1e-11 * max(abs(lhs), 1.0), (N0, N1, n0, n1)
+        # ortho scale too
+        lhs = np.vdot(g, orc.swdft2d(x, n0, n1, norm="ortho"))
+        rhs = np.vdot(orc.swdft2d_adjoint(g, N0, N1, norm="ortho"), x)
+        assert abs(lhs - rhs) < 1e-11 * max(abs(lhs), 1.0)
+
+
+def pin_adjoint_sampled(orc):
+    """Sampled adjoint pixels equal the same entries of the full adjoint."""
+    rng = np.random.default_rng(19)
+    N0, N1, n0, n1 = 14, 12, 4, 4
+    g = rng.standard_normal((N0 - n0 + 1, N1 - n1 + 1, n0, n1)) + 0j
+    full = orc.swdft2d_adjoint(g, N0, N1)
+    r, c = workloads.pixel_sample(N0, N1, 30, 2)
+    assert np.array_equal(orc.swdft2d_adjoint(g, N0, N1, pixels=(r, c)), full[r, c])
+
+
+def pin_quadratic_fd(orc):
+    """L(x) = sum w |M x|^2 is quadratic, so the central difference with h = 1
+    is exact up to rounding and must equal Re(M^H (2 w M x)) for real x."""
+    rng = np.random.default_rng(20)
+    N0, N1, n0, n1 = 10, 12, 4, 4
+    x = rng.standard_normal((N0, N1))
+    w = (rng.random((n0, n1)) < 0.4).astype(float)
+    w[0, 1] = 1.0
+
+    def loss(z):
+        return float(np.sum(w * np.abs(orc.swdft2d(z, n0, n1)) ** 2))
+
+    grad = orc.swdft2d_adjoint(2.0 * w * orc.swdft2d(x, n0, n1), N0, N1).real
+    for (r, c) in [(0, 0), (N0 - 1, N1 - 1), (3, 7), (0, N1 - 1), (5, 0)]:
+        e = np.zeros_like(x)
+        e[r, c] = 1.0
+        fd = (loss(x + e) - loss(x - e)) / 2.0
+        assert abs(fd - grad[r, c]) < 1e-10 * max(1.0, abs(fd)), (r, c, fd, grad[r, c])
+
+
+ALL_PINS = [pin_matrix_form, pin_fft2, pin_whole_array, pin_exact_small, pin_impulse,
+            pin_constant, pin_onbin_exponential, pin_onbin_cosine, pin_parseval,
+            pin_shift_theorem, pin_linearity_and_sampling, pin_adjoint_dot,
+            pin_adjoint_sampled, pin_quadratic_fd]
