@@ -1,0 +1,211 @@
+"""Throughput of the 2D Tree SWDFT hot path on one MI355X.
+
+Workload: one 1024 x 1024 real FP32 image (N(0,1) plus three planted on-bin
+2D cosines of amplitude 5), 16 x 16 windows -> 1009 x 1009 x 256 complex64
+coefficients (2.085 GB) per step. A step is one forward transform through the
+C ABI with x and y resident in HBM.
+
+Prints one JSON line: coefficients/s of the FP32 tree, the roofline of its
+kernel (HBM-bound: algorithmic bytes = complex64 output + FP32 input per
+launch, over the average launch duration from HIP events on the launch
+stream), the FP64 direct form timed on the same GPU, a write-only probe at the
+same byte count, the normwise relative error on sampled windows, and the FP64
+oracle timed on the host cores on a bounded sample of the same windows.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "SWDFT coeffs/s + % HBM roofline, FP32 tree vs plain FP64 direct @ rel err≤1e-5"
+PEAK_HBM_GBS = 8000.0
+KERNEL_SOURCES = ["paper_1707_08213_amd/csrc/tree_fwd_kernel.h",
+                  "paper_1707_08213_amd/csrc/tree_fwd_n16.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tree_fwd_sin1024_traffic.json")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel source changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def time_launches(fn, steps: int, stream):
+    """Average per-launch duration (ms) from event pairs on `stream`, and the
+    wall time of the whole loop."""
+    import torch
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        starts[i].record(stream)
+        fn()
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    durs = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    return sum(durs) / len(durs), wall, durs
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-comparator", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle sample")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the transform shards over window rows with no exchange; see the design notes)",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1707_08213_amd as swd
+    import workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    wl = workloads.sin1024()
+    x_np = wl["x"]
+    N0, N1 = x_np.shape
+    n0, n1 = wl["n0"], wl["n1"]
+    P0, P1 = N0 - n0 + 1, N1 - n1 + 1
+    x = torch.from_numpy(x_np).to(dev).unsqueeze(0)
+    plan = swd.Plan(N0, N1, n0, n1, torch.float32, batch=1)
+    y = torch.empty(plan.out_shape, dtype=torch.complex64, device=dev)
+    coeffs = plan.output_elems()
+    alg_bytes = plan.output_bytes() + x.numel() * 4
+    stream = torch.cuda.current_stream(dev)
+
+    print(f"[bench] {plan.describe()}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        plan.forward(x, out=y)
+    torch.cuda.synchronize()
+    avg_ms, wall, _ = time_launches(lambda: plan.forward(x, out=y), args.steps, stream)
+    ms_per_step = wall / args.steps * 1e3
+    value = coeffs / (wall / args.steps)
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
+    print(f"[bench] tree: {avg_ms * 1e3:.1f} us/launch, {achieved:.0f} GB/s", file=sys.stderr,
+          flush=True)
+
+    # sampled windows: accuracy (against the oracle in the CPU leg) and spot values
+    q0, q1 = workloads.window_sample(P0, P1, 4096, 2002)
+    got = y[0][torch.from_numpy(q0).to(dev), torch.from_numpy(q1).to(dev)].cpu().numpy()
+
+    # write-only probe at the same byte count
+    swd.write_probe(y)
+    torch.cuda.synchronize()
+    probe_ms, _, _ = time_launches(lambda: swd.write_probe(y), 10, stream)
+    probe_gbs = plan.output_bytes() / (probe_ms * 1e-3) / 1e9
+    del y
+
+    comparator = None
+    if not args.no_comparator:
+        x64 = x.double()
+        p64 = swd.Plan(N0, N1, n0, n1, torch.float64, batch=1, algo="direct_f64")
+        y64 = torch.empty(p64.out_shape, dtype=torch.complex128, device=dev)
+        p64.forward(x64, out=y64)
+        torch.cuda.synchronize()
+        d_ms, d_wall, _ = time_launches(lambda: p64.forward(x64, out=y64), 3, stream)
+        got64 = y64[0][torch.from_numpy(q0).to(dev), torch.from_numpy(q1).to(dev)].cpu().numpy()
+        comparator = {"algo": "direct_f64", "value": coeffs / (d_wall / 3), "unit": "coeffs/s",
+                      "ms_per_step": d_wall / 3 * 1e3, "dtype": "f64",
+                      "tree_speedup": (d_wall / 3) / (wall / args.steps)}
+        del y64, x64
+        torch.cuda.empty_cache()
+        print(f"[bench] direct_f64: {d_ms:.2f} ms/launch", file=sys.stderr, flush=True)
+
+    cpu = None
+    rel_err = None
+    if not args.no_cpu_baseline:
+        import oracle
+        orc = oracle.get()
+        xd = x_np.astype(np.float64)
+        ref = orc.swdft2d(xd, n0, n1, windows=(q0, q1))
+        rel_err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+        if comparator is not None:
+            comparator["rel_err"] = float(np.max(np.abs(got64 - ref)) / np.max(np.abs(ref)))
+        # timed sample sized to about --cpu-seconds of oracle work
+        t0 = time.perf_counter()
+        orc.swdft2d(xd, n0, n1, windows=(q0[:256], q1[:256]))
+        per_win = (time.perf_counter() - t0) / 256
+        nwin = int(min(P0 * P1, max(512, args.cpu_seconds / per_win)))
+        s0, s1 = workloads.window_sample(P0, P1, nwin, 3002)
+        t0 = time.perf_counter()
+        orc.swdft2d(xd, n0, n1, windows=(s0, s1))
+        dt = time.perf_counter() - t0
+        cpu = {"value": s0.size * n0 * n1 / dt, "unit": "coeffs/s", "cores": orc.num_threads(),
+               "kind": "oracle",
+               "sample": f"{s0.size} of the {P0}x{P1} windows (seeded, corners and edges "
+                         f"included), {s0.size * n0 * n1} coefficients in {dt:.1f} s"}
+        print(f"[bench] oracle: {cpu['value']:.3e} coeffs/s on {cpu['cores']} threads",
+              file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "coeffs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "sin1024: one 1024x1024 real FP32 image, N(0,1) + 3 planted on-bin "
+                               "2D cosines (amplitude 5), 16x16 windows, stride 1 -> "
+                               "1009x1009x256 complex64 coefficients",
+                   "N0": N0, "N1": N1, "n0": n0, "n1": n1, "batch": 1, "algo": "tree",
+                   "coeffs_per_step": coeffs},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": measured_traffic(),
+                     "kernel": "tree_fwd_kernel<16,16,real>",
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "avg_launch_us": avg_ms * 1e3},
+        "rel_err": rel_err,
+        "write_probe": {"GB/s": probe_gbs, "frac": probe_gbs / PEAK_HBM_GBS,
+                        "bytes": plan.output_bytes()},
+        "comparator": comparator,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    if rel_err is not None and rel_err > 1e-5:
+        print(f"[bench] accuracy gate failed: rel err {rel_err:.3e} > 1e-5", file=sys.stderr)
+        return 1
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

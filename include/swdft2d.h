@@ -1,0 +1,160 @@
+/*
+ * swdft2d.h - C ABI of the MI355X (gfx950) 2D Tree Sliding-Window DFT library.
+ *
+ * Problem (Sec. 4.1, Eq. (2)): for an N0 x N1 array x and radix-2 windows
+ * n0 = 2^m0, n1 = 2^m1 (n_i <= N_i, non-square allowed), compute for every
+ * window position the 2D DFT of that n0 x n1 window:
+ *
+ *   y[b][q0][q1][k0][k1] = s * sum_{j0<n0} sum_{j1<n1} x[b][q0+j0][q1+j1]
+ *                          * exp(-2 pi i (j0 k0 / n0 + j1 k1 / n1))
+ *
+ * with q_i = p_i - n_i + 1 in [0, P_i), P_i = N_i - n_i + 1 (the paper indexes
+ * windows by their bottom-right corner p_i; the output is stored by the
+ * top-left corner q_i), k_i in [0, n_i). s = 1 by default (the tree's natural,
+ * unnormalised output, which equals a per-window FFT, Sec. 4.6) or
+ * s = 1/sqrt(n0 n1) (the scale printed in Eq. (2)), see swdft2d_set_norm.
+ * The output holds P0*P1*n0*n1 coefficients per image (Sec. 4.1, Sec. 4.3).
+ *
+ * Algorithms (swdft2d_set_algo):
+ *   TREE   - the 2D Tree SWDFT: log2(n1) row levels (Eq. (5)) then log2(n0)
+ *            column levels (Eq. (6)) swept over the whole grid so every
+ *            sub-DFT shared by overlapping windows is computed once per tile.
+ *            FP32 arithmetic, twiddles generated in FP64 and rounded once.
+ *   DENSE_BF16X2 - each window as F_n0 X F_n1^T on the matrix cores, BF16
+ *            hi/lo split products accumulated in FP32.
+ *   DIRECT_F64 - Eq. (2) evaluated literally per coefficient in FP64
+ *            (the comparator; the only algorithm for R64/C64 input).
+ *   AUTO   - TREE for R32/C32, DIRECT_F64 for R64/C64.
+ *
+ * Memory layout (all row-major, contiguous, device memory owned by the caller):
+ *   x  : [batch][N0][N1]  float (R32), float2 interleaved (C32),
+ *                         double (R64), double2 (C64)
+ *   y  : [batch][P0][P1][n0][n1] complex, k1 fastest:
+ *                         float2 for R32/C32, double2 for R64/C64
+ *   dx : layout and type of x; dy : layout and type of y.
+ * For real x the full n0 x n1 spectrum is written (no Hermitian packing).
+ *
+ * Ownership: the caller owns x, y, dx, dy. A plan owns only host state and,
+ * once backward has run, a device workspace it frees in swdft2d_destroy.
+ * Plans never allocate at creation, so plan-time validation needs no GPU.
+ *
+ * Streams: exec and backward only enqueue work on the given stream (0 = the
+ * null stream) and never synchronise. The caller must not destroy a plan, nor
+ * free its buffers, while work enqueued with it is in flight. Calls with one
+ * plan from several host threads must be serialised by the caller.
+ *
+ * Errors: every entry point returns a status and never aborts. All argument
+ * checks happen on the host before anything is enqueued; on an error nothing
+ * is enqueued and outputs are untouched. swdft2d_last_error() gives a
+ * thread-local detail string for the last failing call on this thread.
+ */
+#ifndef SWDFT2D_H
+#define SWDFT2D_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SWDFT_R32 = 0, /* real float input, complex64 output */
+    SWDFT_C32 = 1, /* complex64 input, complex64 output */
+    SWDFT_R64 = 2, /* real double input, complex128 output (DIRECT_F64 only) */
+    SWDFT_C64 = 3  /* complex128 input, complex128 output (DIRECT_F64 only) */
+} swdft_dtype_t;
+
+typedef enum {
+    SWDFT_NORM_NONE = 0,  /* s = 1: the tree's natural output (default) */
+    SWDFT_NORM_ORTHO = 1  /* s = 1/sqrt(n0 n1), as printed in Eq. (2) */
+} swdft_norm_t;
+
+typedef enum {
+    SWDFT_ALGO_AUTO = 0,
+    SWDFT_ALGO_TREE = 1,
+    SWDFT_ALGO_DENSE_BF16X2 = 2,
+    SWDFT_ALGO_DIRECT_F64 = 3
+} swdft_algo_t;
+
+typedef int swdft_status_t;
+#define SWDFT_OK 0
+#define SWDFT_E_ARG 1         /* null pointer, size <= 0, unknown enum value */
+#define SWDFT_E_NOT_POW2 2    /* n0 or n1 is not a power of two (radix-2, Sec. 4.1) */
+#define SWDFT_E_WINDOW 3      /* n_i > N_i, or n_i above SWDFT_MAX_WINDOW */
+#define SWDFT_E_DTYPE 4       /* dtype / algorithm combination not supported */
+#define SWDFT_E_OVERFLOW 5    /* element or byte count does not fit in int64 */
+#define SWDFT_E_NOMEM 6       /* workspace allocation failed */
+#define SWDFT_E_ALIGN 7       /* a buffer is not aligned to its element size */
+#define SWDFT_E_DEVICE 8      /* a HIP call failed; detail in swdft2d_last_error() */
+#define SWDFT_E_PLAN 9        /* null or destroyed plan, or wrong plan kind */
+
+#define SWDFT_MAX_WINDOW 32   /* largest n0 or n1 a plan accepts */
+
+typedef struct swdft2d_plan_s* swdft2d_plan_t;
+
+/* Create a plan for `batch` images of N0 x N1 with n0 x n1 windows.
+ * Checks, in this order: out != NULL (E_ARG); N0, N1, n0, n1, batch >= 1 and
+ * dtype known (E_ARG); n0, n1 powers of two (E_NOT_POW2); n_i <= N_i and
+ * n_i <= SWDFT_MAX_WINDOW (E_WINDOW); batch*P0*P1*n0*n1 and its byte count fit
+ * in int64 (E_OVERFLOW). Builds the twiddle vectors Omega^0, Omega^1 of
+ * Sec. 4.2 in FP64 (exact at quarter turns, Omega[m + n/2] = -Omega[m]) and
+ * rounds them once to FP32. Touches no GPU. On error *out is set to NULL. */
+swdft_status_t swdft2d_plan(swdft2d_plan_t* out, int64_t N0, int64_t N1, int32_t n0, int32_t n1,
+                            swdft_dtype_t dtype, int64_t batch);
+
+/* Select the output scale. Allowed at any time; affects later calls. */
+swdft_status_t swdft2d_set_norm(swdft2d_plan_t plan, swdft_norm_t norm);
+
+/* Select the algorithm. E_DTYPE if it cannot serve the plan's dtype (TREE and
+ * DENSE_BF16X2 serve R32/C32; DIRECT_F64 serves R64/C64, whose callers widen
+ * FP32 data to FP64 exactly beforehand). */
+swdft_status_t swdft2d_set_algo(swdft2d_plan_t plan, swdft_algo_t algo);
+
+/* Forward transform: x (layout above) -> y. Enqueued on `stream`.
+ * E_ARG for null x or y, E_ALIGN if x or y is not aligned to its element
+ * size (4/8/8/16 bytes for x by dtype; 8 or 16 bytes for y), E_ARG if the
+ * byte ranges of x and y overlap. */
+swdft_status_t swdft2d_exec(swdft2d_plan_t plan, const void* x, void* y, hipStream_t stream);
+
+/* Adjoint of the forward map (the conjugate transpose M^H of the linear map
+ * x -> y of Eq. (2) with the plan's scale): dy (layout of y) -> dx (layout of
+ * x). For real dtypes dx = Re(M^H dy), the gradient of a real loss L with
+ * respect to x when dy = dL/dRe(y) + i dL/dIm(y). Computed with the levels of
+ * Eq. (5)-(6) transposed and run in reverse (gather form: deterministic, no
+ * atomics). Supported for R32/C32 with TREE (AUTO) and for R64/C64 with
+ * DIRECT_F64. Errors as for exec. May allocate the plan's workspace on first
+ * use (E_NOMEM on failure). */
+swdft_status_t swdft2d_backward(swdft2d_plan_t plan, const void* dy, void* dx, hipStream_t stream);
+
+/* Free the plan and its workspace. Null is accepted (no-op). The caller must
+ * make sure no work enqueued with the plan is still running. */
+swdft_status_t swdft2d_destroy(swdft2d_plan_t plan);
+
+/* batch*P0*P1*n0*n1, or -1 for a null plan. */
+int64_t swdft2d_output_elems(swdft2d_plan_t plan);
+
+/* Byte size of y (output_elems times 8 or 16), or -1 for a null plan. */
+int64_t swdft2d_output_bytes(swdft2d_plan_t plan);
+
+/* Write a one-line description of the plan's resolved kernel and tiling into
+ * buf (NUL-terminated, truncated to len). Returns the status. */
+swdft_status_t swdft2d_describe(swdft2d_plan_t plan, char* buf, int32_t len);
+
+/* Human-readable name of a status code (static storage). */
+const char* swdft2d_status_string(swdft_status_t status);
+
+/* Detail of the last failing call on the calling thread ("" if none). */
+const char* swdft2d_last_error(void);
+
+/* Measurement aid (not part of the transform): fill `bytes` bytes at y
+ * (8-byte aligned, bytes a multiple of 8) with a constant using the same
+ * store width and cache policy as the tree's output path. Timing it gives the
+ * empirical HBM write ceiling at a given byte count. */
+swdft_status_t swdft2d_write_probe(void* y, int64_t bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWDFT2D_H */

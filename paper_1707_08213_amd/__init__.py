@@ -1,0 +1,201 @@
+"""MI355X-native 2D Tree Sliding-Window DFT (Richardson & Eddy, arXiv 1707.08213).
+
+Python face of libswdft2d.so. PyTorch supplies device memory and the stream;
+every arithmetic step runs in the library's HIP kernels, called through the C
+ABI of include/swdft2d.h (see ``_lib``).
+
+    y = swdft2d(x, n0, n1)              # x: [B,] N0 x N1 on cuda, float32/complex64
+    y.shape == (B, P0, P1, n0, n1)      # P_i = N_i - n_i + 1, complex64
+
+``SWDFT2dFn`` wraps forward and the hand-written adjoint as an autograd
+function.
+"""
+from __future__ import annotations
+
+import ctypes
+import threading
+
+import torch
+
+from . import _lib
+from ._lib import SwdftError, check, lib
+
+__all__ = ["Plan", "swdft2d", "swdft2d_backward", "SWDFT2dFn", "write_probe", "SwdftError",
+           "output_shape"]
+
+_DTYPES = {
+    torch.float32: _lib.SWDFT_R32, torch.complex64: _lib.SWDFT_C32,
+    torch.float64: _lib.SWDFT_R64, torch.complex128: _lib.SWDFT_C64,
+}
+_OUT_DTYPE = {_lib.SWDFT_R32: torch.complex64, _lib.SWDFT_C32: torch.complex64,
+              _lib.SWDFT_R64: torch.complex128, _lib.SWDFT_C64: torch.complex128}
+_NORMS = {"none": _lib.SWDFT_NORM_NONE, "ortho": _lib.SWDFT_NORM_ORTHO}
+_ALGOS = {"auto": _lib.SWDFT_ALGO_AUTO, "tree": _lib.SWDFT_ALGO_TREE,
+          "dense_bf16x2": _lib.SWDFT_ALGO_DENSE_BF16X2, "direct_f64": _lib.SWDFT_ALGO_DIRECT_F64}
+
+
+def output_shape(N0: int, N1: int, n0: int, n1: int, batch: int = 1):
+    return (batch, N0 - n0 + 1, N1 - n1 + 1, n0, n1)
+
+
+class Plan:
+    """One swdft2d plan: `batch` images of N0 x N1, n0 x n1 windows."""
+
+    def __init__(self, N0, N1, n0, n1, dtype=torch.float32, batch=1, norm="none", algo="auto"):
+        if dtype not in _DTYPES:
+            raise TypeError(f"unsupported dtype {dtype}")
+        self.N0, self.N1, self.n0, self.n1, self.batch = int(N0), int(N1), int(n0), int(n1), int(batch)
+        self.dtype = dtype
+        self.code = _DTYPES[dtype]
+        h = ctypes.c_void_p()
+        check(lib.swdft2d_plan(ctypes.byref(h), self.N0, self.N1, self.n0, self.n1, self.code,
+                               self.batch), "swdft2d_plan")
+        self.handle = h
+        try:
+            check(lib.swdft2d_set_norm(h, _NORMS[norm]), "swdft2d_set_norm")
+            check(lib.swdft2d_set_algo(h, _ALGOS[algo]), "swdft2d_set_algo")
+        except Exception:
+            lib.swdft2d_destroy(h)
+            self.handle = None
+            raise
+        self.norm, self.algo = norm, algo
+
+    @property
+    def out_shape(self):
+        return output_shape(self.N0, self.N1, self.n0, self.n1, self.batch)
+
+    @property
+    def out_dtype(self):
+        return _OUT_DTYPE[self.code]
+
+    def output_elems(self) -> int:
+        return int(lib.swdft2d_output_elems(self.handle))
+
+    def output_bytes(self) -> int:
+        return int(lib.swdft2d_output_bytes(self.handle))
+
+    def describe(self) -> str:
+        buf = ctypes.create_string_buffer(512)
+        check(lib.swdft2d_describe(self.handle, buf, 512), "swdft2d_describe")
+        return buf.value.decode()
+
+    # raw-pointer entry points (device addresses as ints)
+    def exec_ptr(self, x_ptr: int, y_ptr: int, stream: int = 0) -> None:
+        check(lib.swdft2d_exec(self.handle, x_ptr, y_ptr, stream), "swdft2d_exec")
+
+    def backward_ptr(self, dy_ptr: int, dx_ptr: int, stream: int = 0) -> None:
+        check(lib.swdft2d_backward(self.handle, dy_ptr, dx_ptr, stream), "swdft2d_backward")
+
+    # tensor entry points
+    def _check_x(self, x: torch.Tensor):
+        want = (self.batch, self.N0, self.N1)
+        if x.dtype != self.dtype or not x.is_cuda or not x.is_contiguous() or \
+                tuple(x.shape) != want:
+            raise ValueError(f"x must be a contiguous cuda {self.dtype} tensor of shape {want}, "
+                             f"got {x.dtype} {tuple(x.shape)} on {x.device}")
+
+    def forward(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        self._check_x(x)
+        if out is None:
+            out = torch.empty(self.out_shape, dtype=self.out_dtype, device=x.device)
+        elif (out.dtype != self.out_dtype or tuple(out.shape) != self.out_shape
+              or not out.is_contiguous() or out.device != x.device):
+            raise ValueError("out has the wrong shape, dtype or device")
+        with torch.cuda.device(x.device):
+            stream = torch.cuda.current_stream(x.device).cuda_stream
+            self.exec_ptr(x.data_ptr(), out.data_ptr(), stream)
+        return out
+
+    def backward(self, dy: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        if dy.dtype != self.out_dtype or tuple(dy.shape) != self.out_shape or \
+                not dy.is_contiguous() or not dy.is_cuda:
+            raise ValueError(f"dy must be a contiguous cuda {self.out_dtype} tensor of shape "
+                             f"{self.out_shape}")
+        if out is None:
+            out = torch.empty((self.batch, self.N0, self.N1), dtype=self.dtype, device=dy.device)
+        with torch.cuda.device(dy.device):
+            stream = torch.cuda.current_stream(dy.device).cuda_stream
+            self.backward_ptr(dy.data_ptr(), out.data_ptr(), stream)
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            check(lib.swdft2d_destroy(self.handle), "swdft2d_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_cache_lock = threading.Lock()
+_plan_cache: dict = {}
+
+
+def _cached_plan(N0, N1, n0, n1, dtype, batch, norm, algo) -> Plan:
+    key = (N0, N1, n0, n1, dtype, batch, norm, algo)
+    with _cache_lock:
+        p = _plan_cache.get(key)
+        if p is None:
+            p = Plan(N0, N1, n0, n1, dtype=dtype, batch=batch, norm=norm, algo=algo)
+            _plan_cache[key] = p
+        return p
+
+
+def _batched(x: torch.Tensor):
+    if x.dim() == 2:
+        return x.unsqueeze(0), True
+    if x.dim() == 3:
+        return x, False
+    raise ValueError("x must be [N0, N1] or [B, N0, N1]")
+
+
+def swdft2d(x: torch.Tensor, n0: int, n1: int, norm: str = "none", algo: str = "auto") -> torch.Tensor:
+    """2D sliding-window DFT of every n0 x n1 window of x ([N0,N1] or [B,N0,N1])."""
+    xb, squeeze = _batched(x.contiguous())
+    B, N0, N1 = xb.shape
+    y = _cached_plan(N0, N1, n0, n1, xb.dtype, B, norm, algo).forward(xb)
+    return y[0] if squeeze else y
+
+
+def swdft2d_backward(dy: torch.Tensor, N0: int, N1: int, dtype=torch.float32, norm: str = "none",
+                     algo: str = "auto") -> torch.Tensor:
+    """Adjoint: dy [B,P0,P1,n0,n1] -> dx [B,N0,N1] (Re of M^H dy for real dtypes)."""
+    squeeze = dy.dim() == 4
+    dyb = dy.unsqueeze(0) if squeeze else dy
+    B, P0, P1, n0, n1 = dyb.shape
+    dx = _cached_plan(N0, N1, n0, n1, dtype, B, norm, algo).backward(dyb.contiguous())
+    return dx[0] if squeeze else dx
+
+
+class SWDFT2dFn(torch.autograd.Function):
+    """y = swdft2d(x); the backward pass runs the library's adjoint kernel.
+
+    For real x and a real loss L, PyTorch hands backward the conjugate
+    Wirtinger gradient dL/dRe(y) + i dL/dIm(y); the gradient with respect to x
+    is Re(M^H of it), which is what the adjoint computes.
+    """
+
+    @staticmethod
+    def forward(ctx, x, n0, n1, norm="none"):
+        ctx.meta = (x.shape, x.dtype, n0, n1, norm)
+        return swdft2d(x, n0, n1, norm=norm)
+
+    @staticmethod
+    def backward(ctx, gy):
+        shape, dtype, n0, n1, norm = ctx.meta
+        N0, N1 = shape[-2], shape[-1]
+        dx = swdft2d_backward(gy.contiguous(), N0, N1, dtype=dtype, norm=norm)
+        return dx.reshape(shape), None, None, None
+
+
+def write_probe(buf: torch.Tensor, nbytes: int | None = None) -> None:
+    """Fill buf with the tree's store pattern (HBM write-ceiling probe)."""
+    if not buf.is_cuda or not buf.is_contiguous():
+        raise ValueError("probe buffer must be a contiguous cuda tensor")
+    nbytes = buf.numel() * buf.element_size() if nbytes is None else nbytes
+    with torch.cuda.device(buf.device):
+        stream = torch.cuda.current_stream(buf.device).cuda_stream
+        check(lib.swdft2d_write_probe(buf.data_ptr(), nbytes, stream), "swdft2d_write_probe")

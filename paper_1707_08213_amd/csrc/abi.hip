@@ -1,0 +1,393 @@
+// Host side of libswdft2d: plan objects, argument validation, twiddle
+// generation and kernel dispatch behind the C ABI of include/swdft2d.h.
+//
+// Plans are plain host objects. Nothing here touches the GPU until exec or
+// backward enqueue work, so every validation path runs on a machine without
+// a GPU.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_set>
+
+#include "internal.h"
+#include "swdft2d.h"
+
+using swdft::TwiddlesF32;
+using swdft::TwiddlesF64;
+
+struct swdft2d_plan_s {
+  int64_t N0 = 0, N1 = 0, P0 = 0, P1 = 0, batch = 0;
+  int32_t n0 = 0, n1 = 0;
+  swdft_dtype_t dtype = SWDFT_R32;
+  swdft_norm_t norm = SWDFT_NORM_NONE;
+  swdft_algo_t algo = SWDFT_ALGO_AUTO;
+  int32_t tree_slab = 0;  // 0 = choose automatically
+  TwiddlesF32 tw32{};
+  TwiddlesF64 tw64{};
+  void* workspace = nullptr;
+  size_t workspace_bytes = 0;
+  int workspace_device = -1;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+std::mutex g_plans_mutex;
+std::unordered_set<swdft2d_plan_s*>& live_plans() {
+  static std::unordered_set<swdft2d_plan_s*> s;
+  return s;
+}
+
+swdft_status_t fail(swdft_status_t st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+swdft_status_t device_fail(hipError_t e, const char* what) {
+  return fail(SWDFT_E_DEVICE, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+bool is_live(swdft2d_plan_t p) {
+  std::lock_guard<std::mutex> lk(g_plans_mutex);
+  return p != nullptr && live_plans().count(p) != 0;
+}
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+bool mul_ok(int64_t a, int64_t b, int64_t* out) {
+  if (a < 0 || b < 0) return false;
+  if (a != 0 && b > INT64_MAX / a) return false;
+  *out = a * b;
+  return true;
+}
+
+bool real_dtype(swdft_dtype_t d) { return d == SWDFT_R32 || d == SWDFT_R64; }
+bool f64_dtype(swdft_dtype_t d) { return d == SWDFT_R64 || d == SWDFT_C64; }
+int64_t x_elem_bytes(swdft_dtype_t d) {
+  switch (d) {
+    case SWDFT_R32: return 4;
+    case SWDFT_C32: return 8;
+    case SWDFT_R64: return 8;
+    default: return 16;
+  }
+}
+int64_t y_elem_bytes(swdft_dtype_t d) { return f64_dtype(d) ? 16 : 8; }
+
+// Omega[m] = exp(-2 pi i m / n), m < n, in FP64. The first half is evaluated
+// with cos/sin except at the exact points m = 0 (1) and m = n/4 (-i); the
+// second half is the exact negation Omega[m + n/2] = -Omega[m].
+void make_twiddles(int n, double2* w) {
+  const double two_pi = 6.283185307179586476925286766559;
+  if (n == 1) {
+    w[0] = make_double2(1.0, 0.0);
+    return;
+  }
+  const int half = n / 2;
+  for (int m = 0; m < half; ++m) {
+    if (m == 0) {
+      w[m] = make_double2(1.0, 0.0);
+    } else if (4 * m == n) {
+      w[m] = make_double2(0.0, -1.0);
+    } else {
+      const double a = two_pi * (double)m / (double)n;
+      w[m] = make_double2(std::cos(a), -std::sin(a));
+    }
+  }
+  for (int m = half; m < n; ++m) w[m] = make_double2(-w[m - half].x, -w[m - half].y);
+}
+
+swdft_algo_t resolve_algo(const swdft2d_plan_s* p) {
+  if (p->algo != SWDFT_ALGO_AUTO) return p->algo;
+  return f64_dtype(p->dtype) ? SWDFT_ALGO_DIRECT_F64 : SWDFT_ALGO_TREE;
+}
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Output rows per wave of the fused tree: enough waves to fill the chip
+// several times over, and a slab long enough that the n0-1 priming rows at its
+// top stay a small fraction of the work.
+int32_t tree_slab(const swdft2d_plan_s* p) {
+  const int cr = swdft::tree_fwd_rows_per_chunk(p->n0, p->n1);
+  const int64_t nstrips = ceil_div(p->P1, swdft::tree_fwd_columns_per_wave(p->n0, p->n1));
+  int64_t S = p->tree_slab;
+  if (S <= 0) {
+    const char* env = std::getenv("SWDFT_TREE_SLAB");
+    if (env) S = std::atoll(env);
+  }
+  if (S <= 0) {
+    const int64_t target_waves = 4096;
+    S = ceil_div(p->P0 * nstrips * p->batch, target_waves);
+    S = std::max<int64_t>(S, 4 * (int64_t)(p->n0 - 1));
+  }
+  S = std::max<int64_t>(S, cr);
+  S = ceil_div(S, cr) * cr;
+  S = std::min<int64_t>(S, ceil_div(p->P0, cr) * cr);
+  return (int32_t)S;
+}
+
+swdft::TreeGeom tree_geom(const swdft2d_plan_s* p) {
+  swdft::TreeGeom g{};
+  g.N0 = p->N0;
+  g.N1 = p->N1;
+  g.P0 = p->P0;
+  g.P1 = p->P1;
+  g.x_image_stride = p->N0 * p->N1;
+  g.y_image_stride = p->P0 * p->P1 * p->n0 * p->n1;
+  g.S = tree_slab(p);
+  g.nstrips = (int32_t)ceil_div(p->P1, swdft::tree_fwd_columns_per_wave(p->n0, p->n1));
+  g.nslabs = (int32_t)ceil_div(p->P0, g.S);
+  g.batch = (int32_t)p->batch;
+  g.scale = p->norm == SWDFT_NORM_ORTHO ? (float)(1.0 / std::sqrt((double)p->n0 * p->n1)) : 1.0f;
+  return g;
+}
+
+swdft::DirectGeom direct_geom(const swdft2d_plan_s* p) {
+  swdft::DirectGeom g{};
+  g.N0 = p->N0;
+  g.N1 = p->N1;
+  g.P0 = p->P0;
+  g.P1 = p->P1;
+  g.x_image_stride = p->N0 * p->N1;
+  g.y_image_stride = p->P0 * p->P1 * p->n0 * p->n1;
+  g.n0 = p->n0;
+  g.n1 = p->n1;
+  g.ntiles1 = (int32_t)ceil_div(p->P1, swdft::direct_f64_windows_per_block(p->n0, p->n1));
+  g.batch = (int32_t)p->batch;
+  g.scale = p->norm == SWDFT_NORM_ORTHO ? 1.0 / std::sqrt((double)p->n0 * p->n1) : 1.0;
+  return g;
+}
+
+bool ranges_overlap(const void* a, int64_t abytes, const void* b, int64_t bbytes) {
+  const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+  return a0 < b0 + (uintptr_t)bbytes && b0 < a0 + (uintptr_t)abytes;
+}
+
+swdft_status_t check_buffers(const swdft2d_plan_s* p, const void* in, int64_t in_align,
+                             int64_t in_bytes, const void* out, int64_t out_align,
+                             int64_t out_bytes, const char* in_name, const char* out_name) {
+  if (!in) return fail(SWDFT_E_ARG, "%s is null", in_name);
+  if (!out) return fail(SWDFT_E_ARG, "%s is null", out_name);
+  if ((uintptr_t)in % (uintptr_t)in_align)
+    return fail(SWDFT_E_ALIGN, "%s is not %lld-byte aligned", in_name, (long long)in_align);
+  if ((uintptr_t)out % (uintptr_t)out_align)
+    return fail(SWDFT_E_ALIGN, "%s is not %lld-byte aligned", out_name, (long long)out_align);
+  if (ranges_overlap(in, in_bytes, out, out_bytes))
+    return fail(SWDFT_E_ARG, "%s and %s overlap", in_name, out_name);
+  (void)p;
+  return SWDFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+swdft_status_t swdft2d_plan(swdft2d_plan_t* out, int64_t N0, int64_t N1, int32_t n0, int32_t n1,
+                            swdft_dtype_t dtype, int64_t batch) {
+  if (!out) return fail(SWDFT_E_ARG, "plan output pointer is null");
+  *out = nullptr;
+  if (N0 < 1 || N1 < 1 || n0 < 1 || n1 < 1 || batch < 1)
+    return fail(SWDFT_E_ARG, "sizes must be >= 1 (N=%lld x %lld, n=%d x %d, batch=%lld)",
+                (long long)N0, (long long)N1, n0, n1, (long long)batch);
+  if ((int)dtype < (int)SWDFT_R32 || (int)dtype > (int)SWDFT_C64)
+    return fail(SWDFT_E_ARG, "unknown dtype %d", (int)dtype);
+  if (!is_pow2(n0) || !is_pow2(n1))
+    return fail(SWDFT_E_NOT_POW2, "window %d x %d is not radix-2", n0, n1);
+  if (n0 > N0 || n1 > N1)
+    return fail(SWDFT_E_WINDOW, "window %d x %d larger than array %lld x %lld", n0, n1,
+                (long long)N0, (long long)N1);
+  if (n0 > SWDFT_MAX_WINDOW || n1 > SWDFT_MAX_WINDOW)
+    return fail(SWDFT_E_WINDOW, "window %d x %d above the supported maximum %d", n0, n1,
+                SWDFT_MAX_WINDOW);
+  const int64_t P0 = N0 - n0 + 1, P1 = N1 - n1 + 1;
+  int64_t t = 0, elems = 0, bytes = 0, xel = 0, xbytes = 0;
+  if (!mul_ok(P0, P1, &t) || !mul_ok(t, (int64_t)n0 * n1, &t) || !mul_ok(t, batch, &elems) ||
+      !mul_ok(elems, y_elem_bytes(dtype), &bytes) || !mul_ok(N0, N1, &xel) ||
+      !mul_ok(xel, batch, &xel) || !mul_ok(xel, x_elem_bytes(dtype), &xbytes))
+    return fail(SWDFT_E_OVERFLOW, "output of %lld images of %lld x %lld with %d x %d windows "
+                "overflows int64", (long long)batch, (long long)N0, (long long)N1, n0, n1);
+  if (batch > INT32_MAX || P0 > INT32_MAX || P1 > INT32_MAX)
+    return fail(SWDFT_E_OVERFLOW, "batch or window count above 2^31-1");
+
+  auto* p = new (std::nothrow) swdft2d_plan_s();
+  if (!p) return fail(SWDFT_E_NOMEM, "host allocation of the plan failed");
+  p->N0 = N0;
+  p->N1 = N1;
+  p->P0 = P0;
+  p->P1 = P1;
+  p->n0 = n0;
+  p->n1 = n1;
+  p->batch = batch;
+  p->dtype = dtype;
+  make_twiddles(n0, p->tw64.w0);
+  make_twiddles(n1, p->tw64.w1);
+  for (int m = 0; m < n0; ++m)
+    p->tw32.w0[m] = make_float2((float)p->tw64.w0[m].x, (float)p->tw64.w0[m].y);
+  for (int m = 0; m < n1; ++m)
+    p->tw32.w1[m] = make_float2((float)p->tw64.w1[m].x, (float)p->tw64.w1[m].y);
+  {
+    std::lock_guard<std::mutex> lk(g_plans_mutex);
+    live_plans().insert(p);
+  }
+  *out = p;
+  return SWDFT_OK;
+}
+
+swdft_status_t swdft2d_set_norm(swdft2d_plan_t plan, swdft_norm_t norm) {
+  if (!is_live(plan)) return fail(SWDFT_E_PLAN, "null or destroyed plan");
+  if (norm != SWDFT_NORM_NONE && norm != SWDFT_NORM_ORTHO)
+    return fail(SWDFT_E_ARG, "unknown norm %d", (int)norm);
+  plan->norm = norm;
+  return SWDFT_OK;
+}
+
+swdft_status_t swdft2d_set_algo(swdft2d_plan_t plan, swdft_algo_t algo) {
+  if (!is_live(plan)) return fail(SWDFT_E_PLAN, "null or destroyed plan");
+  switch (algo) {
+    case SWDFT_ALGO_AUTO: break;
+    case SWDFT_ALGO_TREE:
+    case SWDFT_ALGO_DENSE_BF16X2:
+      if (f64_dtype(plan->dtype))
+        return fail(SWDFT_E_DTYPE, "algorithm %d computes in FP32 and needs an R32/C32 plan",
+                    (int)algo);
+      if (algo == SWDFT_ALGO_DENSE_BF16X2)
+        return fail(SWDFT_E_DTYPE, "the dense BF16x2 algorithm is not available in this build");
+      break;
+    case SWDFT_ALGO_DIRECT_F64:
+      if (!f64_dtype(plan->dtype))
+        return fail(SWDFT_E_DTYPE, "DIRECT_F64 needs an R64/C64 plan (widen FP32 input first)");
+      break;
+    default:
+      return fail(SWDFT_E_ARG, "unknown algorithm %d", (int)algo);
+  }
+  plan->algo = algo;
+  return SWDFT_OK;
+}
+
+swdft_status_t swdft2d_exec(swdft2d_plan_t plan, const void* x, void* y, hipStream_t stream) {
+  if (!is_live(plan)) return fail(SWDFT_E_PLAN, "null or destroyed plan");
+  const swdft2d_plan_s* p = plan;
+  const int64_t xb = p->batch * p->N0 * p->N1 * x_elem_bytes(p->dtype);
+  const int64_t yb = swdft2d_output_bytes(plan);
+  swdft_status_t st = check_buffers(p, x, x_elem_bytes(p->dtype), xb, y, y_elem_bytes(p->dtype),
+                                    yb, "x", "y");
+  if (st != SWDFT_OK) return st;
+  hipError_t e = hipSuccess;
+  switch (resolve_algo(p)) {
+    case SWDFT_ALGO_TREE:
+      e = swdft::launch_tree_fwd(p->n0, p->n1, real_dtype(p->dtype), x,
+                                 static_cast<float2*>(y), tree_geom(p), p->tw32, stream);
+      break;
+    case SWDFT_ALGO_DIRECT_F64:
+      e = swdft::launch_direct_f64(p->n0, p->n1, real_dtype(p->dtype), x,
+                                   static_cast<double2*>(y), direct_geom(p), p->tw64, stream);
+      break;
+    default:
+      return fail(SWDFT_E_DTYPE, "algorithm not available for this plan");
+  }
+  if (e != hipSuccess) return device_fail(e, "forward launch");
+  return SWDFT_OK;
+}
+
+swdft_status_t swdft2d_backward(swdft2d_plan_t plan, const void* dy, void* dx, hipStream_t stream) {
+  if (!is_live(plan)) return fail(SWDFT_E_PLAN, "null or destroyed plan");
+  const swdft2d_plan_s* p = plan;
+  const int64_t xb = p->batch * p->N0 * p->N1 * x_elem_bytes(p->dtype);
+  const int64_t yb = swdft2d_output_bytes(plan);
+  swdft_status_t st = check_buffers(p, dy, y_elem_bytes(p->dtype), yb, dx,
+                                    x_elem_bytes(p->dtype), xb, "dy", "dx");
+  if (st != SWDFT_OK) return st;
+  (void)stream;
+  return fail(SWDFT_E_DTYPE, "backward is not available in this build");
+}
+
+swdft_status_t swdft2d_destroy(swdft2d_plan_t plan) {
+  if (plan == nullptr) return SWDFT_OK;
+  {
+    std::lock_guard<std::mutex> lk(g_plans_mutex);
+    auto it = live_plans().find(plan);
+    if (it == live_plans().end()) return fail(SWDFT_E_PLAN, "plan already destroyed or unknown");
+    live_plans().erase(it);
+  }
+  swdft_status_t st = SWDFT_OK;
+  if (plan->workspace) {
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (plan->workspace_device >= 0) (void)hipSetDevice(plan->workspace_device);
+    hipError_t e = hipFree(plan->workspace);
+    if (cur >= 0) (void)hipSetDevice(cur);
+    if (e != hipSuccess) st = device_fail(e, "workspace free");
+  }
+  delete plan;
+  return st;
+}
+
+int64_t swdft2d_output_elems(swdft2d_plan_t plan) {
+  if (!is_live(plan)) return -1;
+  return plan->batch * plan->P0 * plan->P1 * plan->n0 * plan->n1;
+}
+
+int64_t swdft2d_output_bytes(swdft2d_plan_t plan) {
+  if (!is_live(plan)) return -1;
+  return swdft2d_output_elems(plan) * y_elem_bytes(plan->dtype);
+}
+
+swdft_status_t swdft2d_describe(swdft2d_plan_t plan, char* buf, int32_t len) {
+  if (!is_live(plan)) return fail(SWDFT_E_PLAN, "null or destroyed plan");
+  if (!buf || len < 1) return fail(SWDFT_E_ARG, "describe buffer is null or empty");
+  const swdft2d_plan_s* p = plan;
+  const swdft_algo_t a = resolve_algo(p);
+  if (a == SWDFT_ALGO_TREE) {
+    const swdft::TreeGeom g = tree_geom(p);
+    snprintf(buf, (size_t)len,
+             "algo=tree n=%dx%d N=%lldx%lld batch=%lld cols_per_wave=%d rows_per_chunk=%d "
+             "slab=%d strips=%d slabs=%d waves=%lld",
+             p->n0, p->n1, (long long)p->N0, (long long)p->N1, (long long)p->batch,
+             swdft::tree_fwd_columns_per_wave(p->n0, p->n1),
+             swdft::tree_fwd_rows_per_chunk(p->n0, p->n1), g.S, g.nstrips, g.nslabs,
+             (long long)g.nstrips * g.nslabs * p->batch);
+  } else {
+    snprintf(buf, (size_t)len, "algo=direct_f64 n=%dx%d N=%lldx%lld batch=%lld windows_per_block=%d",
+             p->n0, p->n1, (long long)p->N0, (long long)p->N1, (long long)p->batch,
+             swdft::direct_f64_windows_per_block(p->n0, p->n1));
+  }
+  return SWDFT_OK;
+}
+
+const char* swdft2d_status_string(swdft_status_t s) {
+  switch (s) {
+    case SWDFT_OK: return "SWDFT_OK";
+    case SWDFT_E_ARG: return "SWDFT_E_ARG";
+    case SWDFT_E_NOT_POW2: return "SWDFT_E_NOT_POW2";
+    case SWDFT_E_WINDOW: return "SWDFT_E_WINDOW";
+    case SWDFT_E_DTYPE: return "SWDFT_E_DTYPE";
+    case SWDFT_E_OVERFLOW: return "SWDFT_E_OVERFLOW";
+    case SWDFT_E_NOMEM: return "SWDFT_E_NOMEM";
+    case SWDFT_E_ALIGN: return "SWDFT_E_ALIGN";
+    case SWDFT_E_DEVICE: return "SWDFT_E_DEVICE";
+    case SWDFT_E_PLAN: return "SWDFT_E_PLAN";
+    default: return "SWDFT_E_UNKNOWN";
+  }
+}
+
+const char* swdft2d_last_error(void) { return g_last_error.c_str(); }
+
+swdft_status_t swdft2d_write_probe(void* y, int64_t bytes, hipStream_t stream) {
+  if (!y) return fail(SWDFT_E_ARG, "probe buffer is null");
+  if (bytes <= 0 || bytes % 8) return fail(SWDFT_E_ARG, "probe size must be a positive multiple of 8");
+  if ((uintptr_t)y % 8) return fail(SWDFT_E_ALIGN, "probe buffer is not 8-byte aligned");
+  hipError_t e = swdft::launch_write_probe(static_cast<float2*>(y), bytes / 8, stream);
+  if (e != hipSuccess) return device_fail(e, "probe launch");
+  return SWDFT_OK;
+}
+
+}  // extern "C"

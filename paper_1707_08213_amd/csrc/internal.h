@@ -1,0 +1,62 @@
+// Internal declarations shared by the host plan code and the kernel files of
+// libswdft2d. Nothing here is part of the public C ABI (include/swdft2d.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace swdft {
+
+constexpr int kMaxWindow = 32;
+
+// Twiddle vectors Omega^0 (length n0) and Omega^1 (length n1) of Sec. 4.2,
+// Omega^i[m] = exp(-2 pi i m / n_i), generated in FP64 and rounded once to
+// FP32. Passed to kernels by value (kernel-argument memory, read through the
+// scalar cache: every twiddle a wave uses is uniform across its lanes).
+struct TwiddlesF32 {
+  float2 w0[kMaxWindow];
+  float2 w1[kMaxWindow];
+};
+
+struct TwiddlesF64 {
+  double2 w0[kMaxWindow];
+  double2 w1[kMaxWindow];
+};
+
+// Geometry of one fused tree launch. One wave owns a strip of window columns
+// (q1) and a slab of S output rows (q0) of one image.
+struct TreeGeom {
+  int64_t N0, N1, P0, P1;
+  int64_t x_image_stride;  // elements between images of x
+  int64_t y_image_stride;  // float2 between images of y
+  int32_t S;               // output rows per wave
+  int32_t nstrips;         // ceil(P1 / window columns per wave)
+  int32_t nslabs;          // ceil(P0 / S)
+  int32_t batch;
+  float scale;             // 1 or 1/sqrt(n0 n1)
+};
+
+struct DirectGeom {
+  int64_t N0, N1, P0, P1;
+  int64_t x_image_stride;
+  int64_t y_image_stride;
+  int32_t n0, n1;
+  int32_t ntiles1;  // ceil(P1 / windows per block)
+  int32_t batch;
+  double scale;
+};
+
+// Kernel launchers (defined next to their kernels). They validate nothing:
+// the plan code has checked every argument before calling them.
+hipError_t launch_tree_fwd(int n0, int n1, bool real_input, const void* x, float2* y,
+                           const TreeGeom& g, const TwiddlesF32& tw, hipStream_t stream);
+int tree_fwd_columns_per_wave(int n0, int n1);
+int tree_fwd_rows_per_chunk(int n0, int n1);
+
+hipError_t launch_direct_f64(int n0, int n1, bool real_input, const void* x, double2* y,
+                             const DirectGeom& g, const TwiddlesF64& tw, hipStream_t stream);
+int direct_f64_windows_per_block(int n0, int n1);
+
+hipError_t launch_write_probe(float2* y, int64_t n_float2, hipStream_t stream);
+
+}  // namespace swdft

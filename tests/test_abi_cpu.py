@@ -1,0 +1,154 @@
+"""Host-side checks of libswdft2d.so that need no GPU: the library loads, it
+exports every entry point include/swdft2d.h declares, and plan validation /
+argument checks return the documented status codes before anything is
+enqueued (no call here reaches a kernel)."""
+import ctypes
+import json
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+_lib = pytest.importorskip("paper_1707_08213_amd._lib",
+                           reason="libswdft2d.so not built (python -m paper_1707_08213_amd.build)")
+lib = _lib.lib
+S = _lib.STATUS_CODE
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "swdft2d.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(swdft2d_\w+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = header_functions()
+    assert "swdft2d_plan" in names and "swdft2d_exec" in names and "swdft2d_backward" in names
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in include/swdft2d.h but not exported"
+        assert name in _lib.SIGNATURES, f"{name} has no ctypes signature in the binding"
+
+
+def make_plan(N0, N1, n0, n1, dtype=_lib.SWDFT_R32, batch=1):
+    h = ctypes.c_void_p()
+    st = lib.swdft2d_plan(ctypes.byref(h), N0, N1, n0, n1, dtype, batch)
+    return st, h
+
+
+@pytest.mark.parametrize("args,status", [
+    ((64, 64, 16, 16, 0, 1), "SWDFT_OK"),
+    ((5, 2, 4, 2, 1, 3), "SWDFT_OK"),
+    ((64, 64, 1, 1, 2, 1), "SWDFT_OK"),
+    ((0, 64, 4, 4, 0, 1), "SWDFT_E_ARG"),
+    ((64, 64, 4, 4, 0, 0), "SWDFT_E_ARG"),
+    ((64, 64, 0, 4, 0, 1), "SWDFT_E_ARG"),
+    ((64, 64, 4, 4, 7, 1), "SWDFT_E_ARG"),
+    ((64, 64, 12, 4, 0, 1), "SWDFT_E_NOT_POW2"),
+    ((64, 64, 4, 3, 0, 1), "SWDFT_E_NOT_POW2"),
+    ((8, 64, 16, 4, 0, 1), "SWDFT_E_WINDOW"),
+    ((128, 128, 64, 4, 0, 1), "SWDFT_E_WINDOW"),
+    ((1 << 40, 1 << 40, 32, 32, 0, 1), "SWDFT_E_OVERFLOW"),
+    ((1 << 20, 1 << 20, 32, 32, 0, 1 << 20), "SWDFT_E_OVERFLOW"),
+])
+def test_plan_validation(args, status):
+    st, h = make_plan(*args)
+    assert _lib.STATUS[st] == status, lib.swdft2d_last_error()
+    if st == 0:
+        assert h.value is not None
+        assert lib.swdft2d_destroy(h) == 0
+    else:
+        assert h.value is None
+        assert lib.swdft2d_last_error()
+
+
+def test_null_out_pointer():
+    assert lib.swdft2d_plan(None, 8, 8, 2, 2, 0, 1) == S["SWDFT_E_ARG"]
+
+
+def test_output_size_matches_paper_example():
+    """Sec. 4.3: P0 = P1 = 400, n0 = n1 = 32 gives 163,840,000 complex numbers,
+    2,621,440,000 bytes at 16 bytes each (complex128)."""
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_values.json")))
+    ex = g["output_size_example"]
+    N0 = ex["P0"] + ex["n0"] - 1
+    N1 = ex["P1"] + ex["n1"] - 1
+    st, h = make_plan(N0, N1, ex["n0"], ex["n1"], _lib.SWDFT_R64)
+    assert st == 0
+    assert lib.swdft2d_output_elems(h) == ex["complex_numbers"]
+    assert lib.swdft2d_output_bytes(h) == ex["bytes_complex128"]
+    lib.swdft2d_destroy(h)
+    st, h = make_plan(N0, N1, ex["n0"], ex["n1"], _lib.SWDFT_R32, 3)
+    assert lib.swdft2d_output_elems(h) == 3 * ex["complex_numbers"]
+    assert lib.swdft2d_output_bytes(h) == 3 * ex["complex_numbers"] * 8
+    lib.swdft2d_destroy(h)
+
+
+def test_fig3_shape_sizes():
+    """Fig. 3: a 2 x 5 array with 2 x 4 windows has two window positions."""
+    f = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_values.json")))["fig3_shape"]
+    st, h = make_plan(f["N0"], f["N1"], f["n0"], f["n1"])
+    assert st == 0
+    assert lib.swdft2d_output_elems(h) == f["windows"] * f["n0"] * f["n1"]
+    lib.swdft2d_destroy(h)
+
+
+def test_exec_argument_checks_do_not_launch():
+    st, h = make_plan(64, 64, 16, 16)
+    assert st == 0
+    # null pointers
+    assert lib.swdft2d_exec(h, None, 0x10000, None) == S["SWDFT_E_ARG"]
+    assert lib.swdft2d_exec(h, 0x10000, None, None) == S["SWDFT_E_ARG"]
+    # misaligned input (float needs 4 bytes) and output (float2 needs 8 bytes)
+    assert lib.swdft2d_exec(h, 0x10001, 0x90000000, None) == S["SWDFT_E_ALIGN"]
+    assert lib.swdft2d_exec(h, 0x10000, 0x90000004, None) == S["SWDFT_E_ALIGN"]
+    # overlapping input and output
+    assert lib.swdft2d_exec(h, 0x10000, 0x10000 + 64, None) == S["SWDFT_E_ARG"]
+    assert b"overlap" in lib.swdft2d_last_error()
+    # backward: same checks with the roles swapped
+    assert lib.swdft2d_backward(h, None, 0x10000, None) == S["SWDFT_E_ARG"]
+    assert lib.swdft2d_backward(h, 0x10004, 0x90000000, None) == S["SWDFT_E_ALIGN"]
+    lib.swdft2d_destroy(h)
+
+
+def test_destroyed_plan_is_rejected():
+    st, h = make_plan(32, 32, 4, 4)
+    assert lib.swdft2d_destroy(h) == 0
+    assert lib.swdft2d_exec(h, 0x10000, 0x90000000, None) == S["SWDFT_E_PLAN"]
+    assert lib.swdft2d_set_norm(h, 1) == S["SWDFT_E_PLAN"]
+    assert lib.swdft2d_output_elems(h) == -1
+    assert lib.swdft2d_destroy(h) == S["SWDFT_E_PLAN"]
+    assert lib.swdft2d_destroy(None) == 0
+
+
+def test_algo_dtype_rules():
+    st, h = make_plan(32, 32, 4, 4, _lib.SWDFT_R32)
+    assert lib.swdft2d_set_algo(h, _lib.SWDFT_ALGO_TREE) == 0
+    assert lib.swdft2d_set_algo(h, _lib.SWDFT_ALGO_DIRECT_F64) == S["SWDFT_E_DTYPE"]
+    assert lib.swdft2d_set_algo(h, 17) == S["SWDFT_E_ARG"]
+    assert lib.swdft2d_set_norm(h, 5) == S["SWDFT_E_ARG"]
+    assert lib.swdft2d_set_norm(h, 1) == 0
+    lib.swdft2d_destroy(h)
+    st, h = make_plan(32, 32, 4, 4, _lib.SWDFT_C64)
+    assert lib.swdft2d_set_algo(h, _lib.SWDFT_ALGO_TREE) == S["SWDFT_E_DTYPE"]
+    assert lib.swdft2d_set_algo(h, _lib.SWDFT_ALGO_DIRECT_F64) == 0
+    lib.swdft2d_destroy(h)
+
+
+def test_describe_and_status_strings():
+    st, h = make_plan(1024, 1024, 16, 16)
+    buf = ctypes.create_string_buffer(256)
+    assert lib.swdft2d_describe(h, buf, 256) == 0
+    d = buf.value.decode()
+    assert "algo=tree" in d and "n=16x16" in d
+    lib.swdft2d_destroy(h)
+    for code, name in _lib.STATUS.items():
+        assert lib.swdft2d_status_string(code).decode() == name
+    assert lib.swdft2d_status_string(99) == b"SWDFT_E_UNKNOWN"
+
+
+def test_write_probe_checks():
+    assert lib.swdft2d_write_probe(None, 64, None) == S["SWDFT_E_ARG"]
+    assert lib.swdft2d_write_probe(0x10000, 12, None) == S["SWDFT_E_ARG"]
+    assert lib.swdft2d_write_probe(0x10004, 16, None) == S["SWDFT_E_ALIGN"]

@@ -1,0 +1,201 @@
+"""Forward parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerance: normwise relative max error max|y_gpu - y_ref| / max|y_ref| <= 1e-5
+for the FP32 tree (the target the workload states; the measured error is
+~2e-7), <= 1e-12 for the FP64 direct kernel. Integer inputs with n_i <= 4 are
+bit exact (every twiddle is a power of -i).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL_F32 = 1e-5
+TOL_F64 = 1e-12
+
+
+@pytest.fixture(scope="module")
+def swd():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_1707_08213_amd as swd
+    return swd
+
+
+def rel_err(got, ref):
+    return float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300))
+
+
+def gpu_full(swd, x_np, n0, n1, norm="none", algo="auto"):
+    x = torch.from_numpy(np.ascontiguousarray(x_np)).cuda()
+    print(f"[case] N={x_np.shape} n={n0}x{n1} dtype={x_np.dtype} norm={norm} algo={algo}",
+          flush=True)
+    y = swd.swdft2d(x, n0, n1, norm=norm, algo=algo)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+SHAPES = [(n0, n1) for n0 in (1, 2, 4, 8, 16, 32) for n1 in (1, 2, 4, 8, 16, 32)]
+
+
+@pytest.mark.parametrize("n0,n1", SHAPES, ids=lambda v: str(v))
+def test_tree_every_window_shape_real(swd, orc, n0, n1):
+    # several strips and slabs plus ragged right and bottom tails
+    N0 = 3 * n0 + 37
+    N1 = 2 * (64 // n1) + n1 + 5
+    x = workloads.normal_real((N0, N1), seed=100 + n0 * 64 + n1)
+    y = gpu_full(swd, x, n0, n1)
+    ref = orc.swdft2d(x.astype(np.float64), n0, n1)
+    assert y.shape == ref.shape
+    assert rel_err(y, ref) <= TOL_F32
+
+
+@pytest.mark.parametrize("n0,n1", [(32, 8), (16, 16), (8, 32), (4, 2), (1, 16), (32, 1)],
+                         ids=lambda v: str(v))
+def test_tree_complex_input(swd, orc, n0, n1):
+    x = workloads.normal_complex((2 * n0 + 29, 3 * (64 // n1) + n1 + 3), seed=7 + n0 + n1)
+    y = gpu_full(swd, x, n0, n1)
+    ref = orc.swdft2d(x.astype(np.complex128), n0, n1)
+    assert rel_err(y, ref) <= TOL_F32
+
+
+def test_tree_ortho_scale(swd, orc):
+    x = workloads.normal_real((70, 90), seed=3)
+    y = gpu_full(swd, x, 16, 8, norm="ortho")
+    ref = orc.swdft2d(x.astype(np.float64), 16, 8, norm="ortho")
+    assert rel_err(y, ref) <= TOL_F32
+    y1 = gpu_full(swd, x, 16, 8)
+    # n0 n1 = 128: the ortho scale is 2^-3.5, applied once to the row DFTs
+    assert rel_err(y1 / np.sqrt(128.0), y) <= 1e-6
+
+
+def test_tree_batched(swd, orc):
+    x = workloads.normal_real((3, 41, 77), seed=9)
+    xt = torch.from_numpy(x).cuda()
+    y = swd.swdft2d(xt, 8, 16).cpu().numpy()
+    for b in range(3):
+        ref = orc.swdft2d(x[b].astype(np.float64), 8, 16)
+        assert rel_err(y[b], ref) <= TOL_F32
+
+
+def test_tree_exact_on_integer_fig3_shape(swd):
+    """Fig. 3 shape (2 x 5 array, 2 x 4 windows) and a larger n <= 4 case with
+    small integers: every twiddle is a power of -i, every partial sum is an
+    exactly representable integer, so the FP32 tree must be bit exact."""
+    rng = np.random.default_rng(5)
+    for (N0, N1, n0, n1) in [(2, 5, 2, 4), (37, 53, 4, 4), (9, 70, 2, 2)]:
+        x = rng.integers(-8, 9, size=(N0, N1)).astype(np.float32)
+        y = gpu_full(swd, x, n0, n1)
+        ref = oracle.swdft2d(x.astype(np.float64), n0, n1)
+        assert np.array_equal(y.astype(np.complex128), ref)
+
+
+def test_tree_whole_array_window(swd, orc):
+    """N = n: one window, the plain 2D DFT of the array."""
+    x = workloads.normal_real((32, 16), seed=4)
+    y = gpu_full(swd, x, 32, 16)
+    assert y.shape == (1, 1, 32, 16)
+    assert rel_err(y[0, 0], np.fft.fft2(x.astype(np.float64))) <= TOL_F32
+
+
+def test_tree_closed_forms(swd):
+    """Impulse and constant inputs give their closed forms on the GPU too."""
+    N0, N1, n0, n1 = 40, 50, 8, 16
+    x = np.zeros((N0, N1), np.float32)
+    r, c = 17, 23
+    x[r, c] = 1.0
+    y = gpu_full(swd, x, n0, n1)
+    k0 = np.arange(n0)[:, None]
+    k1 = np.arange(n1)[None, :]
+    for q0 in range(N0 - n0 + 1):
+        for q1 in range(N1 - n1 + 1):
+            if q0 <= r < q0 + n0 and q1 <= c < q1 + n1:
+                ref = np.exp(-2j * np.pi * ((r - q0) * k0 / n0 + (c - q1) * k1 / n1))
+                assert np.max(np.abs(y[q0, q1] - ref)) < 1e-6
+            else:
+                assert np.all(y[q0, q1] == 0)
+    y = gpu_full(swd, np.full((N0, N1), 2.0, np.float32), n0, n1)
+    expect = np.zeros((n0, n1), complex)
+    expect[0, 0] = 2.0 * n0 * n1
+    assert np.max(np.abs(y - expect)) < 1e-5 * 2.0 * n0 * n1
+
+
+def test_tree_deterministic(swd):
+    x = torch.from_numpy(workloads.normal_real((300, 300), seed=8)).cuda()
+    a = swd.swdft2d(x, 16, 16)
+    b = swd.swdft2d(x, 16, 16)
+    torch.cuda.synchronize()
+    assert torch.equal(torch.view_as_real(a), torch.view_as_real(b))
+
+
+def test_direct_f64_small64(swd, orc):
+    """64 x 64 real FP64, 4 x 4 windows: FP64 direct kernel against the oracle
+    (<= 1e-12) and the FP32 tree on the FP32-rounded copy (<= 1e-5)."""
+    w = workloads.small64()
+    ref = orc.swdft2d(w["x"], 4, 4)
+    y64 = gpu_full(swd, w["x"], 4, 4)
+    assert y64.dtype == np.complex128
+    assert rel_err(y64, ref) <= TOL_F64
+    x32 = w["x"].astype(np.float32)
+    y32 = gpu_full(swd, x32, 4, 4)
+    assert rel_err(y32, orc.swdft2d(x32.astype(np.float64), 4, 4)) <= TOL_F32
+
+
+@pytest.mark.parametrize("n0,n1,cplx", [(16, 16, False), (32, 8, True), (1, 32, False),
+                                        (8, 1, True), (32, 32, False)])
+def test_direct_f64_shapes(swd, orc, n0, n1, cplx):
+    shape = (n0 + 19, n1 + 23)
+    x = workloads.normal_complex(shape, 31, np.complex128) if cplx else \
+        workloads.normal_real(shape, 31, np.float64)
+    y = gpu_full(swd, x, n0, n1)
+    assert rel_err(y, orc.swdft2d(x, n0, n1)) <= TOL_F64
+
+
+def sampled_check(swd, orc, x_np, n0, n1, count, seed):
+    x = torch.from_numpy(x_np).cuda()
+    print(f"[case] full-size N={x_np.shape} n={n0}x{n1}", flush=True)
+    y = swd.swdft2d(x, n0, n1)
+    P0, P1 = x_np.shape[0] - n0 + 1, x_np.shape[1] - n1 + 1
+    q0, q1 = workloads.window_sample(P0, P1, count, seed)
+    got = y[torch.from_numpy(q0).cuda(), torch.from_numpy(q1).cuda()].cpu().numpy()
+    xr = x_np.astype(np.complex128 if np.iscomplexobj(x_np) else np.float64)
+    ref = orc.swdft2d(xr, n0, n1, windows=(q0, q1))
+    del y
+    torch.cuda.empty_cache()
+    return got, ref
+
+
+def test_sin1024_sampled(swd, orc):
+    """1024 x 1024 real FP32 + 3 planted on-bin cosines, 16 x 16 windows:
+    4096 sampled windows (corners and edges included) against the oracle, and
+    the planted bins carry their amplitude."""
+    w = workloads.sin1024()
+    got, ref = sampled_check(swd, orc, w["x"], 16, 16, 4096, 1002)
+    assert rel_err(got, ref) <= TOL_F32
+    for (k0, k1, _ph) in w["planted"]:
+        # each planted cosine puts 5*256/2 = 640 into bin (k0,k1); noise adds O(16)
+        assert np.median(np.abs(got[:, k0, k1])) > 500
+
+
+def test_cplx2048_sampled(swd, orc):
+    """2048 x 512 complex64, 32 x 8 windows, 4096 sampled windows."""
+    w = workloads.cplx2048()
+    got, ref = sampled_check(swd, orc, w["x"], 32, 8, 4096, 1003)
+    assert rel_err(got, ref) <= TOL_F32
+
+
+def test_binding_rejects_bad_tensors(swd):
+    p = swd.Plan(64, 64, 8, 8)
+    with pytest.raises(ValueError):
+        p.forward(torch.zeros(1, 64, 65, device="cuda"))
+    with pytest.raises(ValueError):
+        p.forward(torch.zeros(1, 64, 64, device="cuda", dtype=torch.float64))
+    base = torch.zeros(1 + 64 * 64, device="cuda")
+    with pytest.raises(swd.SwdftError) as e:
+        p.exec_ptr(base.data_ptr() + 2, torch.empty(p.out_shape, dtype=torch.complex64,
+                                                    device="cuda").data_ptr())
+    assert e.value.name == "SWDFT_E_ALIGN"
