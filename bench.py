@@ -53,6 +53,50 @@ def measured_traffic():
     return t.get("hbm_bytes_per_launch")
 
 
+def pmc_summary(fetch_db: str, write_db: str, copy_bytes: int, out_json: str) -> str:
+    """Turn two rocprofv3 --pmc databases (FETCH_SIZE, then WRITE_SIZE, KiB per
+    dispatch) into per-kernel HBM bytes. Each counter is scaled by what it reads
+    for the runtime's plain device copy of `copy_bytes` bytes (run by
+    --copy-calibration). Writes the tree kernel's bytes per launch, tagged with
+    the hash of its source, to `out_json`; returns a markdown table."""
+    import collections
+    import sqlite3
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    for path, counter in ((fetch_db, "FETCH_SIZE"), (write_db, "WRITE_SIZE")):
+        con = sqlite3.connect(path)
+        for name, v in con.execute("select kernel_name, value from counters_collection "
+                                   "where counter_name = ?", (counter,)):
+            vals[name][counter].append(float(v))
+        con.close()
+    copy = [k for k in vals if "copyBuffer" in k]
+    if not copy:
+        raise SystemExit("no device copy kernel in the counter databases")
+    kib = copy_bytes / 1024.0
+    mean = lambda xs: sum(xs) / len(xs)
+    f_scale = kib / mean(vals[copy[0]]["FETCH_SIZE"])
+    w_scale = kib / mean(vals[copy[0]]["WRITE_SIZE"])
+    lines = ["| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM read B | HBM write B |",
+             "|---|---|---|---|---|---|"]
+    tree_bytes = None
+    for name, c in sorted(vals.items()):
+        f, w = mean(c["FETCH_SIZE"]), mean(c["WRITE_SIZE"])
+        rb, wb = f * f_scale * 1024, w * w_scale * 1024
+        short = name.replace("(anonymous namespace)", "anon").split("(")[0][:60]
+        lines.append(f"| {short} | {len(c['FETCH_SIZE'])} | {f:.1f} | {w:.1f} | {rb:.4g} | {wb:.4g} |")
+        if "tree_fwd_kernel<16, 16, true>" in name:
+            tree_bytes = rb + wb
+    lines.append("")
+    lines.append(f"copy reference: {copy_bytes} B read and written; scale FETCH x{f_scale:.4f}, "
+                 f"WRITE x{w_scale:.4f}")
+    if tree_bytes is not None:
+        with open(out_json, "w") as fh:
+            json.dump({"kernel": "tree_fwd_kernel<16,16,real>", "workload": "sin1024",
+                       "kernel_hash": kernel_hash(), "hbm_bytes_per_launch": tree_bytes,
+                       "fetch_scale": f_scale, "write_scale": w_scale}, fh, indent=1)
+            fh.write("\n")
+    return "\n".join(lines)
+
+
 def time_launches(fn, steps: int, stream):
     """Average per-launch duration (ms) from event pairs on `stream`, and the
     wall time of the whole loop."""
@@ -78,9 +122,19 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparator", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="target CPU time of the oracle sample")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain device copy of the output's size (reference for "
+                         "hardware byte counters)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="summarise two rocprofv3 --pmc databases and exit (no GPU needed)")
     args = ap.parse_args()
+    if args.pmc_summary:
+        # copy size = output bytes of the workload (1009*1009*256 complex64)
+        print(pmc_summary(args.pmc_summary[0], args.pmc_summary[1], 1009 * 1009 * 256 * 8,
+                          TRAFFIC_FILE))
+        return 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the transform shards over window rows with no exchange; see the design notes)",
@@ -108,6 +162,15 @@ def main() -> int:
     stream = torch.cuda.current_stream(dev)
 
     print(f"[bench] {plan.describe()}", file=sys.stderr, flush=True)
+    if args.copy_calibration:
+        src = torch.ones(plan.output_bytes() // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: 3 copies of {src.numel() * 4} bytes", file=sys.stderr,
+              flush=True)
+        del src, dst
     for _ in range(args.warmup):
         plan.forward(x, out=y)
     torch.cuda.synchronize()
