@@ -122,9 +122,11 @@ swdft_status_t swdft2d_exec(swdft2d_plan_t plan, const void* x, void* y, hipStre
  * x). For real dtypes dx = Re(M^H dy), the gradient of a real loss L with
  * respect to x when dy = dL/dRe(y) + i dL/dIm(y). Computed with the levels of
  * Eq. (5)-(6) transposed and run in reverse (gather form: deterministic, no
- * atomics). Supported for R32/C32 with TREE (AUTO) and for R64/C64 with
- * DIRECT_F64. Errors as for exec. May allocate the plan's workspace on first
- * use (E_NOMEM on failure). */
+ * atomics). Supported for R32/C32 plans with TREE (or AUTO); E_DTYPE
+ * otherwise. Errors as for exec. Allocates the plan's workspace (partial sums
+ * of (64/n1 + n1 - 1) x-columns per strip of 64/n1 window columns, about
+ * (1 + n1^2/64) times the size of dx) on first use, or when called on another
+ * device, with hipMalloc (E_NOMEM on failure); later calls reuse it. */
 swdft_status_t swdft2d_backward(swdft2d_plan_t plan, const void* dy, void* dx, hipStream_t stream);
 
 /* Free the plan and its workspace. Null is accepted (no-op). The caller must

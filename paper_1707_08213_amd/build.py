@@ -14,8 +14,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIBRARY = os.path.join(PKG, "libswdft2d.so")
-SOURCES = ["abi.hip", "tree_fwd.hip", "direct_f64.hip"] + [
-    f"tree_fwd_n{n}.hip" for n in (1, 2, 4, 8, 16, 32)]
+SOURCES = ["abi.hip", "tree_fwd.hip", "tree_adj.hip", "direct_f64.hip"] + [
+    f"tree_{kind}_n{n}.hip" for kind in ("fwd", "adj") for n in (1, 2, 4, 8, 16, 32)]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

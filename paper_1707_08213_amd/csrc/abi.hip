@@ -151,6 +151,75 @@ swdft::TreeGeom tree_geom(const swdft2d_plan_s* p) {
   return g;
 }
 
+// dx rows per wave of the adjoint: a whole image column when that already
+// gives enough waves (no dy row is then read twice); otherwise slabs, each
+// primed by the n0-1 window rows below it.
+int32_t adj_slab(const swdft2d_plan_s* p) {
+  const int cr = swdft::tree_adj_rows_per_chunk(p->n0, p->n1);
+  const int64_t nstrips = ceil_div(p->P1, swdft::tree_fwd_columns_per_wave(p->n0, p->n1));
+  const int64_t full = ceil_div(p->N0, cr) * cr;
+  int64_t S = 0;
+  const char* env = std::getenv("SWDFT_ADJ_SLAB");
+  if (env) S = std::atoll(env);
+  if (S <= 0) {
+    const int64_t waves_full = nstrips * p->batch;
+    if (waves_full >= 768) {
+      S = full;
+    } else {
+      S = ceil_div(p->N0 * waves_full, 1024);
+      S = std::max<int64_t>(S, 8 * (int64_t)(p->n0 - 1));
+    }
+  }
+  S = std::max<int64_t>(S, cr);
+  S = ceil_div(S, cr) * cr;
+  S = std::min<int64_t>(S, full);
+  return (int32_t)S;
+}
+
+swdft::AdjGeom adj_geom(const swdft2d_plan_s* p) {
+  swdft::AdjGeom g{};
+  g.N0 = p->N0;
+  g.N1 = p->N1;
+  g.P0 = p->P0;
+  g.P1 = p->P1;
+  g.y_image_stride = p->P0 * p->P1 * p->n0 * p->n1;
+  g.S = adj_slab(p);
+  g.nstrips = (int32_t)ceil_div(p->P1, swdft::tree_fwd_columns_per_wave(p->n0, p->n1));
+  g.nslabs = (int32_t)ceil_div(p->N0, g.S);
+  g.batch = (int32_t)p->batch;
+  g.scale = p->norm == SWDFT_NORM_ORTHO ? (float)(1.0 / std::sqrt((double)p->n0 * p->n1)) : 1.0f;
+  return g;
+}
+
+// Make sure the plan's workspace holds `bytes` on the current device.
+swdft_status_t ensure_workspace(swdft2d_plan_s* p, size_t bytes) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return device_fail(e, "hipGetDevice");
+  if (p->workspace && p->workspace_device == dev && p->workspace_bytes >= bytes) return SWDFT_OK;
+  if (p->workspace) {
+    // the previous buffer may still be in use by work on another device/stream
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return device_fail(e, "hipDeviceSynchronize");
+    int cur = dev;
+    if (p->workspace_device >= 0 && p->workspace_device != dev) (void)hipSetDevice(p->workspace_device);
+    (void)hipFree(p->workspace);
+    if (cur != p->workspace_device) (void)hipSetDevice(cur);
+    p->workspace = nullptr;
+    p->workspace_bytes = 0;
+  }
+  void* ptr = nullptr;
+  e = hipMalloc(&ptr, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SWDFT_E_NOMEM, "workspace of %zu bytes: %s", bytes, hipGetErrorString(e));
+  }
+  p->workspace = ptr;
+  p->workspace_bytes = bytes;
+  p->workspace_device = dev;
+  return SWDFT_OK;
+}
+
 swdft::DirectGeom direct_geom(const swdft2d_plan_s* p) {
   swdft::DirectGeom g{};
   g.N0 = p->N0;
@@ -306,8 +375,19 @@ swdft_status_t swdft2d_backward(swdft2d_plan_t plan, const void* dy, void* dx, h
   swdft_status_t st = check_buffers(p, dy, y_elem_bytes(p->dtype), yb, dx,
                                     x_elem_bytes(p->dtype), xb, "dy", "dx");
   if (st != SWDFT_OK) return st;
-  (void)stream;
-  return fail(SWDFT_E_DTYPE, "backward is not available in this build");
+  if (resolve_algo(p) != SWDFT_ALGO_TREE)
+    return fail(SWDFT_E_DTYPE, "backward runs the transposed tree; it needs an R32/C32 plan "
+                "with the TREE (or AUTO) algorithm");
+  const swdft::AdjGeom g = adj_geom(p);
+  const size_t ws_bytes =
+      (size_t)swdft::tree_adj_workspace_elems(p->n0, p->n1, g) * (real_dtype(p->dtype) ? 4 : 8);
+  st = ensure_workspace(plan, ws_bytes);
+  if (st != SWDFT_OK) return st;
+  hipError_t e = swdft::launch_tree_adj(p->n0, p->n1, real_dtype(p->dtype),
+                                        static_cast<const float2*>(dy), p->workspace, dx, g,
+                                        p->tw32, stream);
+  if (e != hipSuccess) return device_fail(e, "adjoint launch");
+  return SWDFT_OK;
 }
 
 swdft_status_t swdft2d_destroy(swdft2d_plan_t plan) {

@@ -36,6 +36,19 @@ struct TreeGeom {
   float scale;             // 1 or 1/sqrt(n0 n1)
 };
 
+// Geometry of one adjoint launch. One wave owns a strip of window columns and
+// a slab of S rows of dx; it writes its partial sums for the QW + n1 - 1 x
+// columns its windows touch to the workspace.
+struct AdjGeom {
+  int64_t N0, N1, P0, P1;
+  int64_t y_image_stride;  // float2 between images of dy
+  int32_t S;               // dx rows per wave
+  int32_t nstrips;         // ceil(P1 / window columns per wave)
+  int32_t nslabs;          // ceil(N0 / S)
+  int32_t batch;
+  float scale;
+};
+
 struct DirectGeom {
   int64_t N0, N1, P0, P1;
   int64_t x_image_stride;
@@ -52,6 +65,12 @@ hipError_t launch_tree_fwd(int n0, int n1, bool real_input, const void* x, float
                            const TreeGeom& g, const TwiddlesF32& tw, hipStream_t stream);
 int tree_fwd_columns_per_wave(int n0, int n1);
 int tree_fwd_rows_per_chunk(int n0, int n1);
+
+hipError_t launch_tree_adj(int n0, int n1, bool real_input, const float2* dy, void* ws, void* dx,
+                           const AdjGeom& g, const TwiddlesF32& tw, hipStream_t stream);
+int tree_adj_rows_per_chunk(int n0, int n1);
+// workspace elements (float for real input, float2 for complex) of one adjoint launch
+int64_t tree_adj_workspace_elems(int n0, int n1, const AdjGeom& g);
 
 hipError_t launch_direct_f64(int n0, int n1, bool real_input, const void* x, double2* y,
                              const DirectGeom& g, const TwiddlesF64& tw, hipStream_t stream);

@@ -1,0 +1,325 @@
+// Adjoint of the 2D Tree SWDFT for gfx950: dx = M^H dy, where M is the
+// linear map x -> y of the forward transform (Eq. (2), computed by the
+// levels of Eq. (5)-(6)).
+//
+// The forward map is a product of level maps; its adjoint is the product of
+// the transposed level maps in reverse order. For a column level u (shift
+// s = n0/2^u, h = 2^{u-1}, w_i = Omega0[i s]) the forward node pair
+//   T_u[p][i] = T_{u-1}[p-s][i] + w_i T_{u-1}[p][i],  T_u[p][i+h] = T_{u-1}[p-s][i] - w_i T_{u-1}[p][i]
+// transposes to
+//   G_{u-1}[p][i] = (G_u[p+s][i] + G_u[p+s][i+h]) + conj(w_i) (G_u[p][i] - G_u[p][i+h]),
+// so the column adjoint streams UP the image (descending p) and keeps, per
+// level, the pair sums S_u[p][i] = G_u[p][i] + G_u[p][i+h] of the last s
+// positions in a register ring: the same n0/2 values per level as the
+// forward ring. G_{m0}[p] is dy of the window whose last row is p (zero where
+// that window does not exist, which also gives the incomplete trees of
+// Sec. 4.7 zero gradient), and G_0[p] = dZ[p], the cotangent of the row DFTs.
+//
+// The row adjoint transposes the per-position row levels: from dZ[q1][k1] it
+// forms the contribution of window column q1 to x[p0][q1 .. q1+n1-1] (an
+// unnormalised inverse DFT computed by the transposed levels), and adds the
+// contributions of the window columns of the wave's strip (overlap-add).
+//
+// Mapping: like the forward kernel, one wave owns QW = 64/n1 window columns
+// and a slab of output rows of dx. Lane (c, k1) reads dy[q0][q1][k0][k1] for
+// all k0 (each load instruction covers whole 128-byte lines), two steps ahead
+// of use (register prefetch) so a wave keeps two rows of loads in flight.
+// The slab is primed by the n0-1 window rows below it. A strip's row adjoint
+// covers x columns [q1_0, q1_0 + QW + n1 - 1); columns near strip edges get
+// parts from neighbouring strips, so each wave writes its partial sums for
+// its QW + n1 - 1 columns to a workspace and a second small kernel adds the
+// at most ceil((QW+n1-1)/QW) partials of each dx element in a fixed order
+// (deterministic, no atomics). dy is read once per slab (plus the priming
+// rows); everything else stays on chip.
+#pragma once
+#include <type_traits>
+
+#include "tree_fwd_kernel.h"
+
+namespace swdft {
+namespace tree {
+
+// conj(Omega[IDX]) * d for IDX < N/2 known at compile time.
+template <int IDX, int N>
+__device__ __forceinline__ float2 twmul_conj(float2 d, const float2* w) {
+  if constexpr (IDX == 0) {
+    return d;
+  } else if constexpr (4 * IDX == N) {
+    return make_float2(-d.y, d.x);  // conj(-i) = i
+  } else {
+    const float2 t = w[IDX];
+    return make_float2(t.x * d.x + t.y * d.y, t.x * d.y - t.y * d.x);
+  }
+}
+
+// Transposed column levels u = m0..1 for one row p (descending order).
+// On entry g[k0] = G_{m0}[p][k0]; returns G_0[p] = dZ[p]. ring[u-1] holds
+// S_u of the next s_u rows below p (already processed); slot (p mod s_u)*h.
+// PM = p mod (n0/2), known at compile time.
+template <int N0W, int PM, int RING, int NLEV>
+__device__ __forceinline__ float2 column_levels_adj(const float2 (&g)[N0W],
+                                                    float2 (&ring)[NLEV][RING],
+                                                    const float2* w0) {
+  constexpr int M0 = ilog2(N0W);
+  float2 cur[N0W];
+  sfor<0, N0W>([&](auto K) { cur[K] = g[K]; });
+  sfor<0, M0>([&](auto V) {
+    constexpr int u = M0 - V;  // M0 .. 1
+    constexpr int s = N0W >> u;
+    constexpr int h = 1 << (u - 1);
+    constexpr int slot = (PM % s) * h;
+    float2 nxt[N0W];
+    sfor<0, h>([&](auto I) {
+      constexpr int i = I;
+      const float2 a = cur[i];
+      const float2 b = cur[i + h];
+      const float2 below = ring[u - 1][slot + i];
+      ring[u - 1][slot + i] = cadd(a, b);
+      nxt[i] = cadd(below, twmul_conj<i * s, N0W>(csub(a, b), w0));
+    });
+    sfor<0, h>([&](auto K) { cur[K] = nxt[K]; });
+  });
+  return cur[0];
+}
+
+// Transposed row levels t = m1..1 for one tree position p. On entry
+// v[k1] = dZ[k1]; on exit v[d] is the cotangent of x[p - d], d < n1.
+template <int N1W>
+__device__ __forceinline__ void row_levels_adj(float2 (&v)[N1W], const float2* w1) {
+  constexpr int M1 = ilog2(N1W);
+  sfor<0, M1>([&](auto V) {
+    constexpr int t = M1 - V;  // M1 .. 1
+    constexpr int s = N1W >> t;
+    constexpr int h = 1 << (t - 1);
+    float2 nv[N1W];
+    sfor<0, s>([&](auto D) {
+      constexpr int d = D;
+      sfor<0, h>([&](auto I) {
+        constexpr int i = I;
+        const float2 a = v[d * 2 * h + i];
+        const float2 b = v[d * 2 * h + i + h];
+        nv[(d + s) * h + i] = cadd(a, b);
+        nv[d * h + i] = twmul_conj<i * s, N1W>(csub(a, b), w1);
+      });
+    });
+    sfor<0, N1W>([&](auto K) { v[K] = nv[K]; });
+  });
+}
+
+__device__ __forceinline__ float2 load_nt(const float2* p) {
+  const f2v t = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(p));
+  return make_float2(t.x, t.y);
+}
+
+template <int N0W, int N1W>
+struct AdjCfg {
+  static constexpr int M0 = ilog2(N0W);
+  static constexpr int QW = 64 / N1W;
+  static constexpr int R = N1W;
+  static constexpr int RING = N0W > 1 ? N0W / 2 : 1;
+  static constexpr int PF = 2;                              // prefetch depth (rows)
+  static constexpr int CR0 = R > RING ? R : RING;
+  static constexpr int CR = CR0 > PF ? CR0 : PF;           // rows per chunk
+  static constexpr int ZS = N1W + 1;
+  static constexpr int ZROW = QW * ZS;
+  static constexpr int NLEV = M0 > 0 ? M0 : 1;
+  static constexpr int WCOLS = QW + N1W - 1;                // x columns a strip touches
+};
+
+template <int N0W, int N1W, bool REAL>
+__global__ __launch_bounds__(64) void tree_adj_kernel(const float2* __restrict__ dy,
+                                                      void* __restrict__ wsv, AdjGeom g,
+                                                      TwiddlesF32 tw) {
+  using C = AdjCfg<N0W, N1W>;
+  __shared__ float2 zl[C::CR * C::ZROW];
+
+  const int lane = threadIdx.x;
+  int id = xcd_tile(blockIdx.x, gridDim.x);
+  const int strip = id % g.nstrips;
+  id /= g.nstrips;
+  const int slab = id % g.nslabs;
+  const int b = id / g.nslabs;
+
+  const int64_t q1_0 = (int64_t)strip * C::QW;
+  const int64_t r0 = (int64_t)slab * g.S;            // first dx row of the slab
+  const int64_t r1 = min(r0 + (int64_t)g.S, g.N0);   // one past the last
+  // positions run from p_top down to r0; p_top = r1 + n0 - 2 rounded up so
+  // that p_top + 1 is a multiple of CR (static ring slots).
+  const int64_t p_hi = r1 + N0W - 2;
+  const int64_t nsteps_min = p_hi - r0 + 1;
+  const int nchunks = (int)((nsteps_min + C::CR - 1) / C::CR);
+  const int64_t p_top = r0 + (int64_t)nchunks * C::CR - 1;
+  const int64_t q0_last = min(r1 - 1, g.P0 - 1);     // last window row read by this slab
+
+  const float2* dyimg = dy + b * g.y_image_stride;
+
+  // column-phase roles
+  const int cp_c = lane / N1W;
+  const int cp_k1 = lane % N1W;
+  const int64_t cp_q1 = q1_0 + cp_c;
+  const bool cp_ok = cp_q1 < g.P1;
+  const float2* dycol = dyimg + cp_q1 * (N0W * N1W) + cp_k1;
+  const int64_t y_row_stride = g.P1 * (N0W * N1W);
+  // row-phase roles
+  const int rp_r = lane / C::QW;
+  const int rp_c = lane % C::QW;
+
+  float2 ring[C::NLEV][C::RING];
+  sfor<0, C::NLEV>([&](auto L) {
+    sfor<0, C::RING>([&](auto K) { ring[L][K] = make_float2(0.f, 0.f); });
+  });
+
+  auto load_step = [&](int64_t gstep, float2 (&dst)[N0W]) {
+    const int64_t p = p_top - gstep;
+    const int64_t q0 = p - (N0W - 1);
+    const bool ok = cp_ok && q0 >= 0 && q0 <= q0_last && p >= r0;
+    const float2* src = dycol + q0 * y_row_stride;
+    sfor<0, N0W>([&](auto K) {
+      dst[K] = ok ? load_nt(src + K * N1W) : make_float2(0.f, 0.f);
+    });
+  };
+
+  float2 pf[C::PF][N0W];
+  sfor<0, C::PF>([&](auto S) { load_step(S, pf[S]); });
+
+  float* wsr = reinterpret_cast<float*>(wsv);
+  float2* wsc = reinterpret_cast<float2*>(wsv);
+  const int64_t ws_strip = ((int64_t)b * g.nstrips + strip) * g.N0;  // row base of this strip
+
+  for (int c = 0; c < nchunks; ++c) {
+    const int64_t cbase = (int64_t)c * C::CR;
+    // chunk rows p = p_top - cbase - st; LDS row st holds dZ[p]
+    sfor<0, C::CR>([&](auto STc) {
+      constexpr int st = STc;
+      constexpr int slot = st % C::PF;
+      float2 gcur[N0W];
+      sfor<0, N0W>([&](auto K) { gcur[K] = pf[slot][K]; });
+      load_step(cbase + st + C::PF, pf[slot]);
+      float2 dz;
+      if constexpr (N0W == 1) {
+        dz = gcur[0];
+      } else {
+        // p mod (n0/2): p_top + 1 is a multiple of CR, hence of n0/2
+        constexpr int pm = (C::RING - 1 - (st % C::RING));
+        dz = column_levels_adj<N0W, pm>(gcur, ring, tw.w0);
+      }
+      zl[st * C::ZROW + cp_c * C::ZS + cp_k1] = dz;
+    });
+    __syncthreads();
+
+    // row adjoint for the chunk rows inside [r0, r1), R rows per pass
+    sfor<0, C::CR / C::R>([&](auto PS) {
+      constexpr int ps = PS;
+      const int st = ps * C::R + rp_r;
+      float2* zrow = zl + st * C::ZROW + rp_c * C::ZS;
+      float2 v[N1W];
+      sfor<0, N1W>([&](auto K) { v[K] = zrow[K]; });
+      row_levels_adj<N1W>(v, tw.w1);
+      // contribution to column q1_0 + rp_c + j is v[n1-1-j]; keep it in place
+      const bool keep = (q1_0 + rp_c) < g.P1;
+      sfor<0, N1W>([&](auto K) {
+        zrow[K] = keep ? v[N1W - 1 - K] : make_float2(0.f, 0.f);
+      });
+      __syncthreads();
+      // overlap-add the QW window columns of each row: QW + n1 - 1 partial sums
+      for (int o = lane; o < C::R * C::WCOLS; o += 64) {
+        const int rr = o / C::WCOLS;
+        const int col = o % C::WCOLS;
+        const int srow = ps * C::R + rr;
+        const int64_t prow = p_top - cbase - srow;
+        float2 acc = make_float2(0.f, 0.f);
+        const int c_lo = col - (N1W - 1) > 0 ? col - (N1W - 1) : 0;
+        const int c_hi = col < C::QW - 1 ? col : C::QW - 1;
+        for (int cc = c_lo; cc <= c_hi; ++cc) {
+          acc = cadd(acc, zl[srow * C::ZROW + cc * C::ZS + (col - cc)]);
+        }
+        if (prow >= r0 && prow < r1) {
+          const int64_t idx = (ws_strip + prow) * C::WCOLS + col;
+          if constexpr (REAL) {
+            wsr[idx] = acc.x * g.scale;
+          } else {
+            wsc[idx] = make_float2(acc.x * g.scale, acc.y * g.scale);
+          }
+        }
+      }
+      __syncthreads();
+    });
+  }
+}
+
+// dx[b][r][c] = sum over strips s whose columns [s*QW, s*QW + QW + n1 - 1)
+// contain c of ws[b][s][r][c - s*QW], in ascending s.
+template <int N1W, bool REAL>
+__global__ __launch_bounds__(256) void tree_adj_reduce_kernel(const void* __restrict__ wsv,
+                                                              void* __restrict__ dxv, AdjGeom g) {
+  constexpr int QW = 64 / N1W;
+  constexpr int WCOLS = QW + N1W - 1;
+  const int64_t total = (int64_t)g.batch * g.N0 * g.N1;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int64_t cidx = i % g.N1;
+  const int64_t rest = i / g.N1;
+  const int64_t r = rest % g.N0;
+  const int64_t b = rest / g.N0;
+  int64_t s_lo = cidx - (WCOLS - 1);
+  s_lo = s_lo > 0 ? (s_lo + QW - 1) / QW : 0;
+  int64_t s_hi = cidx / QW;
+  if (s_hi > g.nstrips - 1) s_hi = g.nstrips - 1;
+  if constexpr (REAL) {
+    const float* ws = reinterpret_cast<const float*>(wsv);
+    float acc = 0.f;
+    for (int64_t s = s_lo; s <= s_hi; ++s)
+      acc += ws[((b * g.nstrips + s) * g.N0 + r) * WCOLS + (cidx - s * QW)];
+    reinterpret_cast<float*>(dxv)[i] = acc;
+  } else {
+    const float2* ws = reinterpret_cast<const float2*>(wsv);
+    float2 acc = make_float2(0.f, 0.f);
+    for (int64_t s = s_lo; s <= s_hi; ++s)
+      acc = cadd(acc, ws[((b * g.nstrips + s) * g.N0 + r) * WCOLS + (cidx - s * QW)]);
+    reinterpret_cast<float2*>(dxv)[i] = acc;
+  }
+}
+
+template <int N0W, int N1W, bool REAL>
+hipError_t launch_adj_one(const float2* dy, void* ws, void* dx, const AdjGeom& g,
+                          const TwiddlesF32& tw, hipStream_t stream) {
+  const int64_t nb = (int64_t)g.batch * g.nslabs * g.nstrips;
+  hipLaunchKernelGGL((tree_adj_kernel<N0W, N1W, REAL>), dim3((unsigned)nb), dim3(64), 0, stream,
+                     dy, ws, g, tw);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t total = (int64_t)g.batch * g.N0 * g.N1;
+  hipLaunchKernelGGL((tree_adj_reduce_kernel<N1W, REAL>), dim3((unsigned)((total + 255) / 256)),
+                     dim3(256), 0, stream, ws, dx, g);
+  return hipGetLastError();
+}
+
+template <int N0W>
+hipError_t launch_adj_n0(int n1, bool real_input, const float2* dy, void* ws, void* dx,
+                         const AdjGeom& g, const TwiddlesF32& tw, hipStream_t s) {
+  switch (n1) {
+#define SWDFT_CASE(N1W)                                                    \
+  case N1W:                                                                \
+    return real_input ? launch_adj_one<N0W, N1W, true>(dy, ws, dx, g, tw, s) \
+                      : launch_adj_one<N0W, N1W, false>(dy, ws, dx, g, tw, s);
+    SWDFT_CASE(1)
+    SWDFT_CASE(2)
+    SWDFT_CASE(4)
+    SWDFT_CASE(8)
+    SWDFT_CASE(16)
+    SWDFT_CASE(32)
+#undef SWDFT_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace tree
+
+hipError_t launch_tree_adj_n0_1(int, bool, const float2*, void*, void*, const AdjGeom&, const TwiddlesF32&, hipStream_t);
+hipError_t launch_tree_adj_n0_2(int, bool, const float2*, void*, void*, const AdjGeom&, const TwiddlesF32&, hipStream_t);
+hipError_t launch_tree_adj_n0_4(int, bool, const float2*, void*, void*, const AdjGeom&, const TwiddlesF32&, hipStream_t);
+hipError_t launch_tree_adj_n0_8(int, bool, const float2*, void*, void*, const AdjGeom&, const TwiddlesF32&, hipStream_t);
+hipError_t launch_tree_adj_n0_16(int, bool, const float2*, void*, void*, const AdjGeom&, const TwiddlesF32&, hipStream_t);
+hipError_t launch_tree_adj_n0_32(int, bool, const float2*, void*, void*, const AdjGeom&, const TwiddlesF32&, hipStream_t);
+
+}  // namespace swdft
