@@ -1,16 +1,21 @@
 """Throughput of the 2D Tree SWDFT hot path on one MI355X.
 
-Workload: one 1024 x 1024 real FP32 image (N(0,1) plus three planted on-bin
-2D cosines of amplitude 5), 16 x 16 windows -> 1009 x 1009 x 256 complex64
-coefficients (2.085 GB) per step. A step is one forward transform through the
-C ABI with x and y resident in HBM.
+Default workload (``--workload sin1024``): one 1024 x 1024 real FP32 image
+(N(0,1) plus three planted on-bin 2D cosines of amplitude 5), 16 x 16
+windows -> 1009 x 1009 x 256 complex64 coefficients (2.085 GB) per step. A
+step is one forward transform through the C ABI with x and y resident in HBM.
 
 Prints one JSON line: coefficients/s of the FP32 tree, the roofline of its
-kernel (HBM-bound: algorithmic bytes = complex64 output + FP32 input per
-launch, over the average launch duration from HIP events on the launch
-stream), the FP64 direct form timed on the same GPU, a write-only probe at the
-same byte count, the normwise relative error on sampled windows, and the FP64
-oracle timed on the host cores on a bounded sample of the same windows.
+kernel (HBM-bound: algorithmic bytes = complex64 output + input per launch,
+over the average launch duration from HIP events on the launch stream), the
+FP64 direct form timed on the same GPU, a write-only probe at the same byte
+count, the normwise relative error on sampled windows, and the FP64 oracle
+timed on the host cores on a bounded sample of the same windows.
+
+Other workloads (one JSON line each, same fields where they apply):
+  cplx2048 - 2048 x 512 complex64, 32 x 8 windows (tree; dense MFMA variant).
+  grad256  - 16 x 256 x 256 real FP32, 16 x 16 windows, forward + adjoint of
+             L = sum w |A|^2 (band mask w); the adjoint kernel is read-bound.
 """
 from __future__ import annotations
 
@@ -28,8 +33,12 @@ if ROOT not in sys.path:
 METRIC = "SWDFT coeffs/s + % HBM roofline, FP32 tree vs plain FP64 direct @ rel err≤1e-5"
 PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ["paper_1707_08213_amd/csrc/tree_fwd_kernel.h",
-                  "paper_1707_08213_amd/csrc/tree_fwd_n16.hip"]
+                  "paper_1707_08213_amd/csrc/tree_fwd_n16_r.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tree_fwd_sin1024_traffic.json")
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_hash() -> str:
@@ -72,7 +81,10 @@ def pmc_summary(fetch_db: str, write_db: str, copy_bytes: int, out_json: str) ->
     if not copy:
         raise SystemExit("no device copy kernel in the counter databases")
     kib = copy_bytes / 1024.0
-    mean = lambda xs: sum(xs) / len(xs)
+
+    def mean(xs):
+        return sum(xs) / len(xs)
+
     f_scale = kib / mean(vals[copy[0]]["FETCH_SIZE"])
     w_scale = kib / mean(vals[copy[0]]["WRITE_SIZE"])
     lines = ["| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM read B | HBM write B |",
@@ -99,7 +111,7 @@ def pmc_summary(fetch_db: str, write_db: str, copy_bytes: int, out_json: str) ->
 
 def time_launches(fn, steps: int, stream):
     """Average per-launch duration (ms) from event pairs on `stream`, and the
-    wall time of the whole loop."""
+    wall time of the whole loop (s), bracketed by device synchronisation."""
     import torch
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
@@ -115,11 +127,239 @@ def time_launches(fn, steps: int, stream):
     return sum(durs) / len(durs), wall, durs
 
 
+def roofline(alg_bytes: int, avg_ms: float, kernel: str, traffic=None) -> dict:
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": kernel,
+            "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_us": avg_ms * 1e3}
+
+
+def oracle_rate(orc, x2d, n0, n1, P0, P1, seconds: float, seed: int):
+    """Time the oracle on a seeded window sample sized to about `seconds`."""
+    import workloads
+    q0, q1 = workloads.window_sample(P0, P1, 256, seed)
+    t0 = time.perf_counter()
+    orc.swdft2d(x2d, n0, n1, windows=(q0, q1))
+    per_win = (time.perf_counter() - t0) / q0.size
+    nwin = int(min(P0 * P1, max(512, seconds / per_win)))
+    s0, s1 = workloads.window_sample(P0, P1, nwin, seed + 1)
+    t0 = time.perf_counter()
+    orc.swdft2d(x2d, n0, n1, windows=(s0, s1))
+    dt = time.perf_counter() - t0
+    return {"value": s0.size * n0 * n1 / dt, "unit": "coeffs/s", "cores": orc.num_threads(),
+            "kind": "oracle",
+            "sample": f"{s0.size} of the {P0}x{P1} windows (seeded, corners and edges "
+                      f"included), {s0.size * n0 * n1} coefficients in {dt:.1f} s"}
+
+
+def base_record(args, value, ms_per_step, dtype, config) -> dict:
+    return {"metric": METRIC, "value": value, "unit": "coeffs/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": config}
+
+
+def forward_leg(plan, x, args, stream):
+    """Warm up and time `plan.forward`; returns (y, avg_ms, wall_per_step_s)."""
+    import torch
+    y = torch.empty(plan.out_shape, dtype=plan.out_dtype, device=x.device)
+    for _ in range(args.warmup):
+        plan.forward(x, out=y)
+    torch.cuda.synchronize()
+    avg_ms, wall, _ = time_launches(lambda: plan.forward(x, out=y), args.steps, stream)
+    return y, avg_ms, wall / args.steps
+
+
+def sampled(y_img, q0, q1):
+    import torch
+    dev = y_img.device
+    return y_img[torch.from_numpy(q0).to(dev), torch.from_numpy(q1).to(dev)].cpu().numpy()
+
+
+def rel(a, b):
+    import numpy as np
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def run_sin1024(args, swd, dev) -> dict:
+    import numpy as np
+    import torch
+
+    import workloads
+    wl = workloads.sin1024()
+    x_np = wl["x"]
+    N0, N1 = x_np.shape
+    n0, n1 = wl["n0"], wl["n1"]
+    P0, P1 = N0 - n0 + 1, N1 - n1 + 1
+    x = torch.from_numpy(x_np).to(dev).unsqueeze(0)
+    plan = swd.Plan(N0, N1, n0, n1, torch.float32, batch=1)
+    coeffs = plan.output_elems()
+    alg_bytes = plan.output_bytes() + x.numel() * 4
+    stream = torch.cuda.current_stream(dev)
+    log(plan.describe())
+    if args.copy_calibration:
+        src = torch.ones(plan.output_bytes() // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {src.numel() * 4} bytes")
+        del src, dst
+    y, avg_ms, step_s = forward_leg(plan, x, args, stream)
+    rf = roofline(alg_bytes, avg_ms, "tree_fwd_kernel<16,16,real>", measured_traffic())
+    log(f"tree: {avg_ms * 1e3:.1f} us/launch, {rf['achieved']:.0f} GB/s")
+    q0, q1 = workloads.window_sample(P0, P1, 4096, 2002)
+    got = sampled(y[0], q0, q1)
+
+    swd.write_probe(y)
+    torch.cuda.synchronize()
+    probe_ms, _, _ = time_launches(lambda: swd.write_probe(y), 10, stream)
+    probe_gbs = plan.output_bytes() / (probe_ms * 1e-3) / 1e9
+    del y
+
+    comparator, got64 = None, None
+    if not args.no_comparator:
+        x64 = x.double()
+        p64 = swd.Plan(N0, N1, n0, n1, torch.float64, batch=1, algo="direct_f64")
+        y64 = torch.empty(p64.out_shape, dtype=torch.complex128, device=dev)
+        p64.forward(x64, out=y64)
+        torch.cuda.synchronize()
+        d_ms, d_wall, _ = time_launches(lambda: p64.forward(x64, out=y64), 3, stream)
+        got64 = sampled(y64[0], q0, q1)
+        comparator = {"algo": "direct_f64", "value": coeffs / (d_wall / 3), "unit": "coeffs/s",
+                      "ms_per_step": d_wall / 3 * 1e3, "avg_launch_ms": d_ms, "dtype": "f64",
+                      "tree_speedup": (d_wall / 3) / step_s}
+        del y64, x64
+        torch.cuda.empty_cache()
+        log(f"direct_f64: {d_ms:.2f} ms/launch")
+
+    cpu, err = None, None
+    if not args.no_cpu_baseline:
+        import oracle
+        orc = oracle.get()
+        xd = x_np.astype(np.float64)
+        ref = orc.swdft2d(xd, n0, n1, windows=(q0, q1))
+        err = rel(got, ref)
+        if got64 is not None:
+            comparator["rel_err"] = rel(got64, ref)
+        cpu = oracle_rate(orc, xd, n0, n1, P0, P1, args.cpu_seconds, 3002)
+        log(f"oracle: {cpu['value']:.3e} coeffs/s on {cpu['cores']} threads")
+
+    out = base_record(args, coeffs / step_s, step_s * 1e3, "f32", {
+        "workload": "sin1024: one 1024x1024 real FP32 image, N(0,1) + 3 planted on-bin "
+                    "2D cosines (amplitude 5), 16x16 windows, stride 1 -> "
+                    "1009x1009x256 complex64 coefficients",
+        "N0": N0, "N1": N1, "n0": n0, "n1": n1, "batch": 1, "algo": "tree",
+        "coeffs_per_step": coeffs})
+    out.update({"roofline": rf, "rel_err": err,
+                "write_probe": {"GB/s": probe_gbs, "frac": probe_gbs / PEAK_HBM_GBS,
+                                "bytes": plan.output_bytes()},
+                "comparator": comparator, "cpu_baseline": cpu})
+    return out
+
+
+def run_cplx2048(args, swd, dev) -> dict:
+    import numpy as np
+    import torch
+
+    import workloads
+    wl = workloads.cplx2048()
+    x_np = wl["x"]
+    N0, N1 = x_np.shape
+    n0, n1 = wl["n0"], wl["n1"]
+    P0, P1 = N0 - n0 + 1, N1 - n1 + 1
+    x = torch.from_numpy(x_np).to(dev).unsqueeze(0)
+    plan = swd.Plan(N0, N1, n0, n1, torch.complex64, batch=1)
+    coeffs = plan.output_elems()
+    alg_bytes = plan.output_bytes() + x.numel() * 8
+    stream = torch.cuda.current_stream(dev)
+    log(plan.describe())
+    y, avg_ms, step_s = forward_leg(plan, x, args, stream)
+    rf = roofline(alg_bytes, avg_ms, "tree_fwd_kernel<32,8,complex>")
+    log(f"tree: {avg_ms * 1e3:.1f} us/launch, {rf['achieved']:.0f} GB/s")
+    q0, q1 = workloads.window_sample(P0, P1, 4096, 2003)
+    got = sampled(y[0], q0, q1)
+    del y
+    cpu, err = None, None
+    if not args.no_cpu_baseline:
+        import oracle
+        orc = oracle.get()
+        xd = x_np.astype(np.complex128)
+        err = rel(got, orc.swdft2d(xd, n0, n1, windows=(q0, q1)))
+        cpu = oracle_rate(orc, xd, n0, n1, P0, P1, args.cpu_seconds, 3003)
+    out = base_record(args, coeffs / step_s, step_s * 1e3, "f32", {
+        "workload": "cplx2048: one 2048x512 complex64 image (re, im N(0,1)), 32x8 windows -> "
+                    "2017x505x256 complex64 coefficients",
+        "N0": N0, "N1": N1, "n0": n0, "n1": n1, "batch": 1, "algo": "tree",
+        "coeffs_per_step": coeffs})
+    out.update({"roofline": rf, "rel_err": err, "cpu_baseline": cpu})
+    return out
+
+
+def run_grad256(args, swd, dev) -> dict:
+    import numpy as np
+    import torch
+
+    import workloads
+    wl = workloads.grad256()
+    x_np, w_np = wl["x"], wl["w"]
+    B, N0, N1 = x_np.shape
+    n0, n1 = wl["n0"], wl["n1"]
+    x = torch.from_numpy(x_np).to(dev)
+    w = torch.from_numpy(w_np).to(dev)
+    plan = swd.Plan(N0, N1, n0, n1, torch.float32, batch=B)
+    coeffs = plan.output_elems()
+    stream = torch.cuda.current_stream(dev)
+    log(plan.describe())
+    y, f_ms, f_step = forward_leg(plan, x, args, stream)
+    dy = 2.0 * w * y
+    dx = torch.empty_like(x)
+    for _ in range(args.warmup):
+        plan.backward(dy, out=dx)
+    torch.cuda.synchronize()
+    b_ms, b_wall, _ = time_launches(lambda: plan.backward(dy, out=dx), args.steps, stream)
+    b_step = b_wall / args.steps
+    rf_f = roofline(plan.output_bytes() + x.numel() * 4, f_ms, "tree_fwd_kernel<16,16,real>")
+    rf_b = roofline(plan.output_bytes() + x.numel() * 4, b_ms,
+                    "tree_adj_kernel<16,16,real> + reduce")
+    log(f"fwd {f_ms * 1e3:.1f} us, bwd {b_ms * 1e3:.1f} us ({rf_b['achieved']:.0f} GB/s)")
+    r, c = workloads.pixel_sample(N0, N1, 256, 55)
+    err = None
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        orc = oracle.get()
+        errs = []
+        t_or, n_or = 0.0, 0
+        for b in (0, B - 1):
+            dyb = dy[b].cpu().numpy().astype(np.complex128)
+            t0 = time.perf_counter()
+            ref = orc.swdft2d_adjoint(dyb, N0, N1, pixels=(r, c)).real
+            t_or += time.perf_counter() - t0
+            n_or += r.size
+            errs.append(rel(dx[b].cpu().numpy()[r, c], ref))
+        err = max(errs)
+        cpu = {"value": n_or / t_or, "unit": "dx pixels/s (adjoint)", "cores": orc.num_threads(),
+               "kind": "oracle", "sample": f"{n_or} sampled pixels of 2 images"}
+    out = base_record(args, coeffs / (f_step + b_step), (f_step + b_step) * 1e3, "f32", {
+        "workload": "grad256: 16 real FP32 256x256 images, 16x16 windows, forward + adjoint of "
+                    "L = sum w|A|^2 (Bernoulli(0.25) band mask)",
+        "N0": N0, "N1": N1, "n0": n0, "n1": n1, "batch": B, "algo": "tree",
+        "coeffs_per_step": coeffs})
+    out.update({"forward_ms": f_step * 1e3, "backward_ms": b_step * 1e3, "roofline": rf_b,
+                "roofline_forward": rf_f, "rel_err": err, "cpu_baseline": cpu})
+    return out
+
+
+WORKLOADS = {"sin1024": run_sin1024, "cplx2048": run_cplx2048, "grad256": run_grad256}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="sin1024", choices=sorted(WORKLOADS) + ["all"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparator", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
@@ -131,7 +371,7 @@ def main() -> int:
                     help="summarise two rocprofv3 --pmc databases and exit (no GPU needed)")
     args = ap.parse_args()
     if args.pmc_summary:
-        # copy size = output bytes of the workload (1009*1009*256 complex64)
+        # copy size = output bytes of the sin1024 workload (1009*1009*256 complex64)
         print(pmc_summary(args.pmc_summary[0], args.pmc_summary[1], 1009 * 1009 * 256 * 8,
                           TRAFFIC_FILE))
         return 0
@@ -141,133 +381,24 @@ def main() -> int:
               file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
 
     import paper_1707_08213_amd as swd
-    import workloads
-
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    wl = workloads.sin1024()
-    x_np = wl["x"]
-    N0, N1 = x_np.shape
-    n0, n1 = wl["n0"], wl["n1"]
-    P0, P1 = N0 - n0 + 1, N1 - n1 + 1
-    x = torch.from_numpy(x_np).to(dev).unsqueeze(0)
-    plan = swd.Plan(N0, N1, n0, n1, torch.float32, batch=1)
-    y = torch.empty(plan.out_shape, dtype=torch.complex64, device=dev)
-    coeffs = plan.output_elems()
-    alg_bytes = plan.output_bytes() + x.numel() * 4
-    stream = torch.cuda.current_stream(dev)
-
-    print(f"[bench] {plan.describe()}", file=sys.stderr, flush=True)
-    if args.copy_calibration:
-        src = torch.ones(plan.output_bytes() // 4, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(f"[bench] copy calibration: 3 copies of {src.numel() * 4} bytes", file=sys.stderr,
-              flush=True)
-        del src, dst
-    for _ in range(args.warmup):
-        plan.forward(x, out=y)
-    torch.cuda.synchronize()
-    avg_ms, wall, _ = time_launches(lambda: plan.forward(x, out=y), args.steps, stream)
-    ms_per_step = wall / args.steps * 1e3
-    value = coeffs / (wall / args.steps)
-    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
-    print(f"[bench] tree: {avg_ms * 1e3:.1f} us/launch, {achieved:.0f} GB/s", file=sys.stderr,
-          flush=True)
-
-    # sampled windows: accuracy (against the oracle in the CPU leg) and spot values
-    q0, q1 = workloads.window_sample(P0, P1, 4096, 2002)
-    got = y[0][torch.from_numpy(q0).to(dev), torch.from_numpy(q1).to(dev)].cpu().numpy()
-
-    # write-only probe at the same byte count
-    swd.write_probe(y)
-    torch.cuda.synchronize()
-    probe_ms, _, _ = time_launches(lambda: swd.write_probe(y), 10, stream)
-    probe_gbs = plan.output_bytes() / (probe_ms * 1e-3) / 1e9
-    del y
-
-    comparator = None
-    if not args.no_comparator:
-        x64 = x.double()
-        p64 = swd.Plan(N0, N1, n0, n1, torch.float64, batch=1, algo="direct_f64")
-        y64 = torch.empty(p64.out_shape, dtype=torch.complex128, device=dev)
-        p64.forward(x64, out=y64)
-        torch.cuda.synchronize()
-        d_ms, d_wall, _ = time_launches(lambda: p64.forward(x64, out=y64), 3, stream)
-        got64 = y64[0][torch.from_numpy(q0).to(dev), torch.from_numpy(q1).to(dev)].cpu().numpy()
-        comparator = {"algo": "direct_f64", "value": coeffs / (d_wall / 3), "unit": "coeffs/s",
-                      "ms_per_step": d_wall / 3 * 1e3, "dtype": "f64",
-                      "tree_speedup": (d_wall / 3) / (wall / args.steps)}
-        del y64, x64
+    names = sorted(WORKLOADS) if args.workload == "all" else [args.workload]
+    if "sin1024" in names:
+        names.remove("sin1024")
+        names.insert(0, "sin1024")
+    rc = 0
+    for name in names:
+        out = WORKLOADS[name](args, swd, dev)
+        print(json.dumps(out), flush=True)
         torch.cuda.empty_cache()
-        print(f"[bench] direct_f64: {d_ms:.2f} ms/launch", file=sys.stderr, flush=True)
-
-    cpu = None
-    rel_err = None
-    if not args.no_cpu_baseline:
-        import oracle
-        orc = oracle.get()
-        xd = x_np.astype(np.float64)
-        ref = orc.swdft2d(xd, n0, n1, windows=(q0, q1))
-        rel_err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
-        if comparator is not None:
-            comparator["rel_err"] = float(np.max(np.abs(got64 - ref)) / np.max(np.abs(ref)))
-        # timed sample sized to about --cpu-seconds of oracle work
-        t0 = time.perf_counter()
-        orc.swdft2d(xd, n0, n1, windows=(q0[:256], q1[:256]))
-        per_win = (time.perf_counter() - t0) / 256
-        nwin = int(min(P0 * P1, max(512, args.cpu_seconds / per_win)))
-        s0, s1 = workloads.window_sample(P0, P1, nwin, 3002)
-        t0 = time.perf_counter()
-        orc.swdft2d(xd, n0, n1, windows=(s0, s1))
-        dt = time.perf_counter() - t0
-        cpu = {"value": s0.size * n0 * n1 / dt, "unit": "coeffs/s", "cores": orc.num_threads(),
-               "kind": "oracle",
-               "sample": f"{s0.size} of the {P0}x{P1} windows (seeded, corners and edges "
-                         f"included), {s0.size * n0 * n1} coefficients in {dt:.1f} s"}
-        print(f"[bench] oracle: {cpu['value']:.3e} coeffs/s on {cpu['cores']} threads",
-              file=sys.stderr, flush=True)
-
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "coeffs/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "sin1024: one 1024x1024 real FP32 image, N(0,1) + 3 planted on-bin "
-                               "2D cosines (amplitude 5), 16x16 windows, stride 1 -> "
-                               "1009x1009x256 complex64 coefficients",
-                   "N0": N0, "N1": N1, "n0": n0, "n1": n1, "batch": 1, "algo": "tree",
-                   "coeffs_per_step": coeffs},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": measured_traffic(),
-                     "kernel": "tree_fwd_kernel<16,16,real>",
-                     "algorithmic_bytes_per_launch": alg_bytes,
-                     "avg_launch_us": avg_ms * 1e3},
-        "rel_err": rel_err,
-        "write_probe": {"GB/s": probe_gbs, "frac": probe_gbs / PEAK_HBM_GBS,
-                        "bytes": plan.output_bytes()},
-        "comparator": comparator,
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(out), flush=True)
-    if rel_err is not None and rel_err > 1e-5:
-        print(f"[bench] accuracy gate failed: rel err {rel_err:.3e} > 1e-5", file=sys.stderr)
-        return 1
-    return 0
+        if out.get("rel_err") is not None and out["rel_err"] > 1e-5:
+            log(f"{name}: accuracy gate failed: rel err {out['rel_err']:.3e} > 1e-5")
+            rc = 1
+    return rc
 
 
 if __name__ == "__main__":

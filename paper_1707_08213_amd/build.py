@@ -15,7 +15,8 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIBRARY = os.path.join(PKG, "libswdft2d.so")
 SOURCES = ["abi.hip", "tree_fwd.hip", "tree_adj.hip", "direct_f64.hip"] + [
-    f"tree_{kind}_n{n}.hip" for kind in ("fwd", "adj") for n in (1, 2, 4, 8, 16, 32)]
+    f"tree_{kind}_n{n}_{t}.hip" for kind in ("fwd", "adj") for n in (1, 2, 4, 8, 16, 32)
+    for t in ("r", "c")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -44,8 +45,11 @@ def _compile(src: str, verbose: bool) -> str:
 
 def build(verbose: bool = False, jobs: int = 8) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    # the largest window instantiations take longest: start them first
+    order = sorted(SOURCES, key=lambda s: -max([int(t[1:]) for t in s[:-4].split("_")
+                                                 if t[:1] == "n" and t[1:].isdigit()] or [0]))
     with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, verbose), order))
     tmp = LIBRARY + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

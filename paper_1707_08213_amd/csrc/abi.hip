@@ -26,6 +26,7 @@ struct swdft2d_plan_s {
   swdft_norm_t norm = SWDFT_NORM_NONE;
   swdft_algo_t algo = SWDFT_ALGO_AUTO;
   int32_t tree_slab = 0;  // 0 = choose automatically
+  int32_t tree_kg = 0;    // 0 = choose automatically
   TwiddlesF32 tw32{};
   TwiddlesF64 tw64{};
   void* workspace = nullptr;
@@ -113,12 +114,23 @@ swdft_algo_t resolve_algo(const swdft2d_plan_s* p) {
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+int32_t tree_kg(const swdft2d_plan_s* p) {
+  int kg = p->tree_kg;
+  if (kg <= 0) {
+    const char* env = std::getenv("SWDFT_TREE_KG");
+    if (env) kg = std::atoi(env);
+  }
+  if (kg <= 0 || !swdft::tree_fwd_kg_supported(p->n0, p->n1, kg))
+    kg = swdft::tree_fwd_default_kg(p->n0, p->n1);
+  return kg;
+}
+
 // Output rows per wave of the fused tree: enough waves to fill the chip
 // several times over, and a slab long enough that the n0-1 priming rows at its
 // top stay a small fraction of the work.
-int32_t tree_slab(const swdft2d_plan_s* p) {
-  const int cr = swdft::tree_fwd_rows_per_chunk(p->n0, p->n1);
-  const int64_t nstrips = ceil_div(p->P1, swdft::tree_fwd_columns_per_wave(p->n0, p->n1));
+int32_t tree_slab(const swdft2d_plan_s* p, int kg) {
+  const int cr = swdft::tree_fwd_rows_per_chunk(p->n0, p->n1, kg);
+  const int64_t nstrips = ceil_div(p->P1, swdft::tree_fwd_columns_per_wave(p->n0, p->n1, kg));
   int64_t S = p->tree_slab;
   if (S <= 0) {
     const char* env = std::getenv("SWDFT_TREE_SLAB");
@@ -143,8 +155,9 @@ swdft::TreeGeom tree_geom(const swdft2d_plan_s* p) {
   g.P1 = p->P1;
   g.x_image_stride = p->N0 * p->N1;
   g.y_image_stride = p->P0 * p->P1 * p->n0 * p->n1;
-  g.S = tree_slab(p);
-  g.nstrips = (int32_t)ceil_div(p->P1, swdft::tree_fwd_columns_per_wave(p->n0, p->n1));
+  g.kg = tree_kg(p);
+  g.S = tree_slab(p, g.kg);
+  g.nstrips = (int32_t)ceil_div(p->P1, swdft::tree_fwd_columns_per_wave(p->n0, p->n1, g.kg));
   g.nslabs = (int32_t)ceil_div(p->P0, g.S);
   g.batch = (int32_t)p->batch;
   g.scale = p->norm == SWDFT_NORM_ORTHO ? (float)(1.0 / std::sqrt((double)p->n0 * p->n1)) : 1.0f;
@@ -156,7 +169,7 @@ swdft::TreeGeom tree_geom(const swdft2d_plan_s* p) {
 // primed by the n0-1 window rows below it.
 int32_t adj_slab(const swdft2d_plan_s* p) {
   const int cr = swdft::tree_adj_rows_per_chunk(p->n0, p->n1);
-  const int64_t nstrips = ceil_div(p->P1, swdft::tree_fwd_columns_per_wave(p->n0, p->n1));
+  const int64_t nstrips = ceil_div(p->P1, swdft::tree_adj_columns_per_wave(p->n0, p->n1));
   const int64_t full = ceil_div(p->N0, cr) * cr;
   int64_t S = 0;
   const char* env = std::getenv("SWDFT_ADJ_SLAB");
@@ -184,7 +197,7 @@ swdft::AdjGeom adj_geom(const swdft2d_plan_s* p) {
   g.P1 = p->P1;
   g.y_image_stride = p->P0 * p->P1 * p->n0 * p->n1;
   g.S = adj_slab(p);
-  g.nstrips = (int32_t)ceil_div(p->P1, swdft::tree_fwd_columns_per_wave(p->n0, p->n1));
+  g.nstrips = (int32_t)ceil_div(p->P1, swdft::tree_adj_columns_per_wave(p->n0, p->n1));
   g.nslabs = (int32_t)ceil_div(p->N0, g.S);
   g.batch = (int32_t)p->batch;
   g.scale = p->norm == SWDFT_NORM_ORTHO ? (float)(1.0 / std::sqrt((double)p->n0 * p->n1)) : 1.0f;
@@ -429,11 +442,11 @@ swdft_status_t swdft2d_describe(swdft2d_plan_t plan, char* buf, int32_t len) {
   if (a == SWDFT_ALGO_TREE) {
     const swdft::TreeGeom g = tree_geom(p);
     snprintf(buf, (size_t)len,
-             "algo=tree n=%dx%d N=%lldx%lld batch=%lld cols_per_wave=%d rows_per_chunk=%d "
+             "algo=tree n=%dx%d N=%lldx%lld batch=%lld kg=%d cols_per_wave=%d rows_per_chunk=%d "
              "slab=%d strips=%d slabs=%d waves=%lld",
-             p->n0, p->n1, (long long)p->N0, (long long)p->N1, (long long)p->batch,
-             swdft::tree_fwd_columns_per_wave(p->n0, p->n1),
-             swdft::tree_fwd_rows_per_chunk(p->n0, p->n1), g.S, g.nstrips, g.nslabs,
+             p->n0, p->n1, (long long)p->N0, (long long)p->N1, (long long)p->batch, g.kg,
+             swdft::tree_fwd_columns_per_wave(p->n0, p->n1, g.kg),
+             swdft::tree_fwd_rows_per_chunk(p->n0, p->n1, g.kg), g.S, g.nstrips, g.nslabs,
              (long long)g.nstrips * g.nslabs * p->batch);
   } else {
     snprintf(buf, (size_t)len, "algo=direct_f64 n=%dx%d N=%lldx%lld batch=%lld windows_per_block=%d",

@@ -33,6 +33,7 @@ struct TreeGeom {
   int32_t nstrips;         // ceil(P1 / window columns per wave)
   int32_t nslabs;          // ceil(P0 / S)
   int32_t batch;
+  int32_t kg;              // lanes per column stream (k0 residues), 1 or 2
   float scale;             // 1 or 1/sqrt(n0 n1)
 };
 
@@ -63,12 +64,16 @@ struct DirectGeom {
 // the plan code has checked every argument before calling them.
 hipError_t launch_tree_fwd(int n0, int n1, bool real_input, const void* x, float2* y,
                            const TreeGeom& g, const TwiddlesF32& tw, hipStream_t stream);
-int tree_fwd_columns_per_wave(int n0, int n1);
-int tree_fwd_rows_per_chunk(int n0, int n1);
+int tree_fwd_columns_per_wave(int n0, int n1, int kg);
+int tree_fwd_rows_per_chunk(int n0, int n1, int kg);
+// lanes per column stream used when the caller does not choose
+int tree_fwd_default_kg(int n0, int n1);
+bool tree_fwd_kg_supported(int n0, int n1, int kg);
 
 hipError_t launch_tree_adj(int n0, int n1, bool real_input, const float2* dy, void* ws, void* dx,
                            const AdjGeom& g, const TwiddlesF32& tw, hipStream_t stream);
 int tree_adj_rows_per_chunk(int n0, int n1);
+int tree_adj_columns_per_wave(int n0, int n1);
 // workspace elements (float for real input, float2 for complex) of one adjoint launch
 int64_t tree_adj_workspace_elems(int n0, int n1, const AdjGeom& g);
 

@@ -9,6 +9,11 @@ int tree_adj_rows_per_chunk(int n0, int n1) {
   return cr > 2 ? cr : 2;
 }
 
+int tree_adj_columns_per_wave(int n0, int n1) {
+  (void)n0;
+  return 64 / n1;
+}
+
 int64_t tree_adj_workspace_elems(int n0, int n1, const AdjGeom& g) {
   (void)n0;
   const int64_t wcols = 64 / n1 + n1 - 1;
@@ -18,12 +23,12 @@ int64_t tree_adj_workspace_elems(int n0, int n1, const AdjGeom& g) {
 hipError_t launch_tree_adj(int n0, int n1, bool real_input, const float2* dy, void* ws, void* dx,
                            const AdjGeom& g, const TwiddlesF32& tw, hipStream_t stream) {
   switch (n0) {
-    case 1: return launch_tree_adj_n0_1(n1, real_input, dy, ws, dx, g, tw, stream);
-    case 2: return launch_tree_adj_n0_2(n1, real_input, dy, ws, dx, g, tw, stream);
-    case 4: return launch_tree_adj_n0_4(n1, real_input, dy, ws, dx, g, tw, stream);
-    case 8: return launch_tree_adj_n0_8(n1, real_input, dy, ws, dx, g, tw, stream);
-    case 16: return launch_tree_adj_n0_16(n1, real_input, dy, ws, dx, g, tw, stream);
-    case 32: return launch_tree_adj_n0_32(n1, real_input, dy, ws, dx, g, tw, stream);
+    case 1: return real_input ? launch_tree_adj_n0_1_r(n1, dy, ws, dx, g, tw, stream) : launch_tree_adj_n0_1_c(n1, dy, ws, dx, g, tw, stream);
+    case 2: return real_input ? launch_tree_adj_n0_2_r(n1, dy, ws, dx, g, tw, stream) : launch_tree_adj_n0_2_c(n1, dy, ws, dx, g, tw, stream);
+    case 4: return real_input ? launch_tree_adj_n0_4_r(n1, dy, ws, dx, g, tw, stream) : launch_tree_adj_n0_4_c(n1, dy, ws, dx, g, tw, stream);
+    case 8: return real_input ? launch_tree_adj_n0_8_r(n1, dy, ws, dx, g, tw, stream) : launch_tree_adj_n0_8_c(n1, dy, ws, dx, g, tw, stream);
+    case 16: return real_input ? launch_tree_adj_n0_16_r(n1, dy, ws, dx, g, tw, stream) : launch_tree_adj_n0_16_c(n1, dy, ws, dx, g, tw, stream);
+    case 32: return real_input ? launch_tree_adj_n0_32_r(n1, dy, ws, dx, g, tw, stream) : launch_tree_adj_n0_32_c(n1, dy, ws, dx, g, tw, stream);
     default: return hipErrorInvalidValue;
   }
 }

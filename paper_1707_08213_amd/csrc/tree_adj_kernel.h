@@ -294,32 +294,37 @@ hipError_t launch_adj_one(const float2* dy, void* ws, void* dx, const AdjGeom& g
   return hipGetLastError();
 }
 
-template <int N0W>
-hipError_t launch_adj_n0(int n1, bool real_input, const float2* dy, void* ws, void* dx,
-                         const AdjGeom& g, const TwiddlesF32& tw, hipStream_t s) {
+template <int N0W, bool REAL>
+hipError_t launch_adj_n0(int n1, const float2* dy, void* ws, void* dx, const AdjGeom& g,
+                         const TwiddlesF32& tw, hipStream_t s) {
   switch (n1) {
-#define SWDFT_CASE(N1W)                                                    \
-  case N1W:                                                                \
-    return real_input ? launch_adj_one<N0W, N1W, true>(dy, ws, dx, g, tw, s) \
-                      : launch_adj_one<N0W, N1W, false>(dy, ws, dx, g, tw, s);
-    SWDFT_CASE(1)
-    SWDFT_CASE(2)
-    SWDFT_CASE(4)
-    SWDFT_CASE(8)
-    SWDFT_CASE(16)
-    SWDFT_CASE(32)
-#undef SWDFT_CASE
+    case 1: return launch_adj_one<N0W, 1, REAL>(dy, ws, dx, g, tw, s);
+    case 2: return launch_adj_one<N0W, 2, REAL>(dy, ws, dx, g, tw, s);
+    case 4: return launch_adj_one<N0W, 4, REAL>(dy, ws, dx, g, tw, s);
+    case 8: return launch_adj_one<N0W, 8, REAL>(dy, ws, dx, g, tw, s);
+    case 16: return launch_adj_one<N0W, 16, REAL>(dy, ws, dx, g, tw, s);
+    case 32: return launch_adj_one<N0W, 32, REAL>(dy, ws, dx, g, tw, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 }  // namespace tree
 
-hipError_t launch_tree_adj_n0_1(int, bool, const float2*, void*, void*, const AdjGeom&, const TwiddlesF32&, hipStream_t);
-hipError_t launch_tree_adj_n0_2(int, bool, const float2*, void*, void*, const AdjGeom&, const TwiddlesF32&, hipStream_t);
-hipError_t launch_tree_adj_n0_4(int, bool, const float2*, void*, void*, const AdjGeom&, const TwiddlesF32&, hipStream_t);
-hipError_t launch_tree_adj_n0_8(int, bool, const float2*, void*, void*, const AdjGeom&, const TwiddlesF32&, hipStream_t);
-hipError_t launch_tree_adj_n0_16(int, bool, const float2*, void*, void*, const AdjGeom&, const TwiddlesF32&, hipStream_t);
-hipError_t launch_tree_adj_n0_32(int, bool, const float2*, void*, void*, const AdjGeom&, const TwiddlesF32&, hipStream_t);
+#define SWDFT_ADJ_DECL(N0W, TAG) \
+  hipError_t launch_tree_adj_n0_##N0W##_##TAG(int, const float2*, void*, void*, const AdjGeom&, \
+                                             const TwiddlesF32&, hipStream_t);
+SWDFT_ADJ_DECL(1, r)
+SWDFT_ADJ_DECL(1, c)
+SWDFT_ADJ_DECL(2, r)
+SWDFT_ADJ_DECL(2, c)
+SWDFT_ADJ_DECL(4, r)
+SWDFT_ADJ_DECL(4, c)
+SWDFT_ADJ_DECL(8, r)
+SWDFT_ADJ_DECL(8, c)
+SWDFT_ADJ_DECL(16, r)
+SWDFT_ADJ_DECL(16, c)
+SWDFT_ADJ_DECL(32, r)
+SWDFT_ADJ_DECL(32, c)
+#undef SWDFT_ADJ_DECL
 
 }  // namespace swdft

@@ -4,25 +4,34 @@
 
 namespace swdft {
 
-int tree_fwd_columns_per_wave(int n0, int n1) {
+int tree_fwd_columns_per_wave(int n0, int n1, int kg) {
   (void)n0;
-  return 64 / n1;
+  return 64 / (n1 * kg);
 }
 
-int tree_fwd_rows_per_chunk(int n0, int n1) {
+int tree_fwd_rows_per_chunk(int n0, int n1, int kg) {
   const int ring = n0 > 1 ? n0 / 2 : 1;
-  return n1 > ring ? n1 : ring;
+  const int rows_per_pass = n1 * kg;
+  return rows_per_pass > ring ? rows_per_pass : ring;
+}
+
+// A stream is split over two lanes when its register rings would otherwise
+// limit the kernel to one wave per SIMD (n0 = 32).
+int tree_fwd_default_kg(int n0, int n1) { return (n0 == 32 && n1 <= 32) ? 2 : 1; }
+
+bool tree_fwd_kg_supported(int n0, int n1, int kg) {
+  return kg == 1 || (kg == 2 && n0 >= 8 && n1 <= 32);
 }
 
 hipError_t launch_tree_fwd(int n0, int n1, bool real_input, const void* x, float2* y,
                            const TreeGeom& g, const TwiddlesF32& tw, hipStream_t stream) {
   switch (n0) {
-    case 1: return launch_tree_fwd_n0_1(n1, real_input, x, y, g, tw, stream);
-    case 2: return launch_tree_fwd_n0_2(n1, real_input, x, y, g, tw, stream);
-    case 4: return launch_tree_fwd_n0_4(n1, real_input, x, y, g, tw, stream);
-    case 8: return launch_tree_fwd_n0_8(n1, real_input, x, y, g, tw, stream);
-    case 16: return launch_tree_fwd_n0_16(n1, real_input, x, y, g, tw, stream);
-    case 32: return launch_tree_fwd_n0_32(n1, real_input, x, y, g, tw, stream);
+    case 1: return real_input ? launch_tree_fwd_n0_1_r(n1, x, y, g, tw, stream) : launch_tree_fwd_n0_1_c(n1, x, y, g, tw, stream);
+    case 2: return real_input ? launch_tree_fwd_n0_2_r(n1, x, y, g, tw, stream) : launch_tree_fwd_n0_2_c(n1, x, y, g, tw, stream);
+    case 4: return real_input ? launch_tree_fwd_n0_4_r(n1, x, y, g, tw, stream) : launch_tree_fwd_n0_4_c(n1, x, y, g, tw, stream);
+    case 8: return real_input ? launch_tree_fwd_n0_8_r(n1, x, y, g, tw, stream) : launch_tree_fwd_n0_8_c(n1, x, y, g, tw, stream);
+    case 16: return real_input ? launch_tree_fwd_n0_16_r(n1, x, y, g, tw, stream) : launch_tree_fwd_n0_16_c(n1, x, y, g, tw, stream);
+    case 32: return real_input ? launch_tree_fwd_n0_32_r(n1, x, y, g, tw, stream) : launch_tree_fwd_n0_32_c(n1, x, y, g, tw, stream);
     default: return hipErrorInvalidValue;
   }
 }

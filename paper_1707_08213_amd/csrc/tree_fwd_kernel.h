@@ -99,34 +99,78 @@ __device__ __forceinline__ void row_levels(float2 (&v)[N1W], const float2* w1) {
   });
 }
 
-// Column levels u = 1..m0 (Eq. (6)) for one new row of a (q1, k1) stream.
-// ring[u-1] holds level u-1 of the last s_u trees: slot (p mod s_u) * 2^{u-1}.
-// The slot read for tree p - s_u is the slot tree p is written to. ST is the
-// row index within the chunk (chunks start at multiples of n0/2).
-template <int N0W, int ST, int RING, int NLEV>
-__device__ __forceinline__ void column_levels(float2 z, float2 (&ring)[NLEV][RING],
-                                              float2 (&out)[N0W], const float2* w0) {
-  constexpr int M0 = ilog2(N0W);
+// Column phase bookkeeping for a stream split over KG lanes (KG = 2^G, a
+// power of two below n0). Lane residue r < KG holds, at level v, the nodes
+// i < 2^v with i = r (mod KG): one node (i = r mod 2^v) while 2^v <= KG, else
+// the 2^v / KG nodes r + KG j. Those nodes depend only on level-(v-1) nodes
+// of the same residue, so the KG lanes never exchange data; the k0 outputs
+// of lane r are k0 = r + KG j.
+template <int N0W, int KG>
+struct ColCfg {
+  static constexpr int M0 = ilog2(N0W);
+  static constexpr int G = ilog2(KG);
+  static constexpr int held(int v) { return v <= G ? 1 : (1 << v) / KG; }
+  // the ring read at level u holds level u-1 of the last s_u = n0/2^u trees
+  static constexpr int ring_size(int u) { return (N0W >> u) * held(u - 1); }
+  static constexpr int ring_off(int u) { return u <= 1 ? 0 : ring_off(u - 1) + ring_size(u - 1); }
+  static constexpr int RING_TOTAL = M0 > 0 ? ring_off(M0 + 1) : 1;
+  static constexpr int OUTS = N0W / KG;  // outputs per lane and row
+};
+
+// Column levels u = 1..m0 (Eq. (6)) for one new row p of a (q1, k1) stream:
+//   T_u[p][i]     = T_{u-1}[p - s_u][i] + Omega0[i s_u] T_{u-1}[p][i]
+//   T_u[p][i + h] = T_{u-1}[p - s_u][i] - Omega0[i s_u] T_{u-1}[p][i]
+// The ring of level u-1 keeps its last s_u trees, slot (p mod s_u); the slot
+// read for tree p - s_u is the slot tree p is written to. ST is the row index
+// within the chunk (chunks start at multiples of n0/2, so p mod s_u = ST mod s_u).
+// For a split stream (KG > 1) the twiddle of node r + KG j is
+// Omega0[(r + KG j) s_u] = lanefac[u] * Omega0[KG j s_u]: a per-lane factor
+// (lanefac[u] = Omega0[(r mod 2^u) s_u]) times a twiddle uniform over the wave.
+// emit(j, v) receives output k0 = r + KG j.
+template <int N0W, int KG, int ST, typename Emit>
+__device__ __forceinline__ void column_levels(float2 z, float2 (&ring)[ColCfg<N0W, KG>::RING_TOTAL],
+                                              const float2 (&lanefac)[ColCfg<N0W, KG>::M0 + 1],
+                                              const float2* w0, Emit&& emit) {
+  using CC = ColCfg<N0W, KG>;
   float2 cur[N0W];
   cur[0] = z;
-  sfor<1, M0 + 1>([&](auto U) {
+  sfor<1, CC::M0 + 1>([&](auto U) {
     constexpr int u = U;
     constexpr int s = N0W >> u;
-    constexpr int h = 1 << (u - 1);
-    constexpr int slot = (ST % s) * h;
-    float2 nxt[N0W];
-    sfor<0, h>([&](auto I) {
-      constexpr int i = I;
-      const float2 b = ring[u - 1][slot + i];
-      const float2 d = cur[i];
-      ring[u - 1][slot + i] = d;
-      const float2 tw = twmul<i * s, N0W>(d, w0);
-      nxt[i] = cadd(b, tw);
-      nxt[i + h] = csub(b, tw);
-    });
-    sfor<0, 2 * h>([&](auto K) { cur[K] = nxt[K]; });
+    constexpr int hp = CC::held(u - 1);
+    constexpr int base = CC::ring_off(u) + (ST % s) * hp;
+    if constexpr (u <= CC::G) {
+      // one node per lane: i_u = r mod 2^u from i_{u-1} = r mod 2^{u-1}
+      const float2 b = ring[base];
+      const float2 d = cur[0];
+      ring[base] = d;
+      const float2 f = lanefac[u];
+      cur[0] = make_float2(b.x + (f.x * d.x - f.y * d.y), b.y + (f.x * d.y + f.y * d.x));
+    } else {
+      float2 nxt[N0W];
+      sfor<0, hp>([&](auto J) {
+        constexpr int j = J;
+        const float2 b = ring[base + j];
+        float2 d = cur[j];
+        ring[base + j] = d;
+        if constexpr (KG > 1) {
+          const float2 f = lanefac[u];
+          d = make_float2(f.x * d.x - f.y * d.y, f.x * d.y + f.y * d.x);
+        }
+        const float2 t = twmul<KG * j * s, N0W>(d, w0);
+        if constexpr (u == CC::M0) {
+          emit(std::integral_constant<int, j>{}, cadd(b, t));
+          emit(std::integral_constant<int, j + hp>{}, csub(b, t));
+        } else {
+          nxt[j] = cadd(b, t);
+          nxt[j + hp] = csub(b, t);
+        }
+      });
+      if constexpr (u < CC::M0) {
+        sfor<0, 2 * hp>([&](auto K) { cur[K] = nxt[K]; });
+      }
+    }
   });
-  sfor<0, N0W>([&](auto K) { out[K] = cur[K]; });
 }
 
 __device__ __forceinline__ void store_nt(float2* p, float2 v) {
@@ -144,23 +188,25 @@ __device__ __forceinline__ int xcd_tile(int id, int nb) {
   return x < r ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
 }
 
-template <int N0W, int N1W, bool REAL>
+template <int N0W, int N1W, bool REAL, int KG>
 struct TreeCfg {
   static constexpr int M0 = ilog2(N0W);
-  static constexpr int QW = 64 / N1W;                       // window columns per wave
-  static constexpr int R = N1W;                             // rows per row pass (64 / QW)
+  static constexpr int QW = 64 / (N1W * KG);                // window columns per wave
+  static constexpr int R = 64 / QW;                         // rows per row pass
   static constexpr int RING = N0W > 1 ? N0W / 2 : 1;        // ring period
   static constexpr int CR = R > RING ? R : RING;            // rows per chunk
   static constexpr int ZS = N1W + 1;                        // padded stride of one window column in LDS
   static constexpr int ZROW = QW * ZS;                      // float2 per chunk row in LDS
-  static constexpr int NLEV = M0 > 0 ? M0 : 1;
+  static_assert(KG == 1 || KG < N0W, "a split stream needs KG < n0");
+  static_assert(N1W * KG <= 64, "one wave must hold a whole window column");
 };
 
-template <int N0W, int N1W, bool REAL>
+template <int N0W, int N1W, bool REAL, int KG>
 __global__ __launch_bounds__(64) void tree_fwd_kernel(const void* __restrict__ xv,
                                                       float2* __restrict__ y, TreeGeom g,
                                                       TwiddlesF32 tw) {
-  using C = TreeCfg<N0W, N1W, REAL>;
+  using C = TreeCfg<N0W, N1W, REAL, KG>;
+  using CC = ColCfg<N0W, KG>;
   __shared__ float2 zl[C::CR * C::ZROW];
 
   const int lane = threadIdx.x;
@@ -180,22 +226,33 @@ __global__ __launch_bounds__(64) void tree_fwd_kernel(const void* __restrict__ x
   const float2* xc = reinterpret_cast<const float2*>(xv) + (REAL ? 0 : b * g.x_image_stride);
   float2* yimg = y + b * g.y_image_stride;
 
-  // row-phase roles
+  // row-phase roles: lane (r, c) = input row r of the pass, window column c
   const int rp_r = lane / C::QW;
   const int rp_c = lane % C::QW;
   const int64_t rp_q1 = q1_0 + rp_c;
-  // column-phase roles
-  const int cp_c = lane / N1W;
+  // column-phase roles: lane (c, res, k1)
+  const int cp_c = lane / (N1W * KG);
+  const int cp_res = (lane / N1W) % KG;
   const int cp_k1 = lane % N1W;
   const int64_t cp_q1 = q1_0 + cp_c;
   const bool cp_ok = cp_q1 < g.P1;
-  float2* ycol = yimg + cp_q1 * (N0W * N1W) + cp_k1;
+  float2* ycol = yimg + cp_q1 * (N0W * N1W) + cp_res * N1W + cp_k1;
   const int64_t y_row_stride = g.P1 * (N0W * N1W);
 
-  float2 ring[C::NLEV][C::RING];
-  sfor<0, C::NLEV>([&](auto L) {
-    sfor<0, C::RING>([&](auto K) { ring[L][K] = make_float2(0.f, 0.f); });
+  float2 lanefac[CC::M0 + 1];
+  lanefac[0] = make_float2(1.f, 0.f);
+  sfor<1, CC::M0 + 1>([&](auto U) {
+    constexpr int u = U;
+    if constexpr (KG > 1) {
+      const int idx = (cp_res & ((1 << u) - 1)) * (N0W >> u);
+      lanefac[u] = tw.w0[idx];
+    } else {
+      lanefac[u] = make_float2(1.f, 0.f);
+    }
   });
+
+  float2 ring[CC::RING_TOTAL];
+  sfor<0, CC::RING_TOTAL>([&](auto K) { ring[K] = make_float2(0.f, 0.f); });
 
   for (int c = 0; c < nchunks; ++c) {
     const int64_t crow = row0 + (int64_t)c * C::CR;
@@ -229,18 +286,15 @@ __global__ __launch_bounds__(64) void tree_fwd_kernel(const void* __restrict__ x
     sfor<0, C::CR>([&](auto STc) {
       constexpr int st = STc;
       const float2 z = zl[st * C::ZROW + cp_c * C::ZS + cp_k1];
-      float2 out[N0W];
-      if constexpr (N0W == 1) {
-        out[0] = z;
-      } else {
-        column_levels<N0W, st % C::RING>(z, ring, out, tw.w0);
-      }
       const int64_t q0 = crow + st - (N0W - 1);
-      if (q0 >= row0 && q0 < q0_end) {
-        if (cp_ok) {
-          float2* dst = ycol + q0 * y_row_stride;
-          sfor<0, N0W>([&](auto K) { store_nt(dst + K * N1W, out[K]); });
-        }
+      const bool store = (q0 >= row0) && (q0 < q0_end) && cp_ok;
+      float2* dst = ycol + q0 * y_row_stride;
+      if constexpr (N0W == 1) {
+        if (store) store_nt(dst, z);
+      } else {
+        column_levels<N0W, KG, st % C::RING>(z, ring, lanefac, tw.w0, [&](auto J, float2 v) {
+          if (store) store_nt(dst + (KG * J) * N1W, v);
+        });
       }
     });
     __syncthreads();
@@ -251,37 +305,51 @@ template <int N0W, int N1W, bool REAL>
 hipError_t launch_one(const void* x, float2* y, const TreeGeom& g, const TwiddlesF32& tw,
                       hipStream_t stream) {
   const int64_t nb = (int64_t)g.batch * g.nslabs * g.nstrips;
-  hipLaunchKernelGGL((tree_fwd_kernel<N0W, N1W, REAL>), dim3((unsigned)nb), dim3(64), 0, stream,
+  if constexpr (N0W >= 8 && N1W <= 32) {
+    if (g.kg == 2) {
+      hipLaunchKernelGGL((tree_fwd_kernel<N0W, N1W, REAL, 2>), dim3((unsigned)nb), dim3(64), 0,
+                         stream, x, y, g, tw);
+      return hipGetLastError();
+    }
+  }
+  if (g.kg != 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((tree_fwd_kernel<N0W, N1W, REAL, 1>), dim3((unsigned)nb), dim3(64), 0, stream,
                      x, y, g, tw);
   return hipGetLastError();
 }
 
-// One translation unit per n0 instantiates launchers for every n1.
-template <int N0W>
-hipError_t launch_n0(int n1, bool real_input, const void* x, float2* y, const TreeGeom& g,
-                     const TwiddlesF32& tw, hipStream_t s) {
+// One translation unit per (n0, input type) instantiates launchers for every n1.
+template <int N0W, bool REAL>
+hipError_t launch_n0(int n1, const void* x, float2* y, const TreeGeom& g, const TwiddlesF32& tw,
+                     hipStream_t s) {
   switch (n1) {
-#define SWDFT_CASE(N1W) \
-  case N1W:             \
-    return real_input ? launch_one<N0W, N1W, true>(x, y, g, tw, s) : launch_one<N0W, N1W, false>(x, y, g, tw, s);
-    SWDFT_CASE(1)
-    SWDFT_CASE(2)
-    SWDFT_CASE(4)
-    SWDFT_CASE(8)
-    SWDFT_CASE(16)
-    SWDFT_CASE(32)
-#undef SWDFT_CASE
+    case 1: return launch_one<N0W, 1, REAL>(x, y, g, tw, s);
+    case 2: return launch_one<N0W, 2, REAL>(x, y, g, tw, s);
+    case 4: return launch_one<N0W, 4, REAL>(x, y, g, tw, s);
+    case 8: return launch_one<N0W, 8, REAL>(x, y, g, tw, s);
+    case 16: return launch_one<N0W, 16, REAL>(x, y, g, tw, s);
+    case 32: return launch_one<N0W, 32, REAL>(x, y, g, tw, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 }  // namespace tree
 
-hipError_t launch_tree_fwd_n0_1(int, bool, const void*, float2*, const TreeGeom&, const TwiddlesF32&, hipStream_t);
-hipError_t launch_tree_fwd_n0_2(int, bool, const void*, float2*, const TreeGeom&, const TwiddlesF32&, hipStream_t);
-hipError_t launch_tree_fwd_n0_4(int, bool, const void*, float2*, const TreeGeom&, const TwiddlesF32&, hipStream_t);
-hipError_t launch_tree_fwd_n0_8(int, bool, const void*, float2*, const TreeGeom&, const TwiddlesF32&, hipStream_t);
-hipError_t launch_tree_fwd_n0_16(int, bool, const void*, float2*, const TreeGeom&, const TwiddlesF32&, hipStream_t);
-hipError_t launch_tree_fwd_n0_32(int, bool, const void*, float2*, const TreeGeom&, const TwiddlesF32&, hipStream_t);
+#define SWDFT_FWD_DECL(N0W, TAG) \
+  hipError_t launch_tree_fwd_n0_##N0W##_##TAG(int, const void*, float2*, const TreeGeom&, \
+                                             const TwiddlesF32&, hipStream_t);
+SWDFT_FWD_DECL(1, r)
+SWDFT_FWD_DECL(1, c)
+SWDFT_FWD_DECL(2, r)
+SWDFT_FWD_DECL(2, c)
+SWDFT_FWD_DECL(4, r)
+SWDFT_FWD_DECL(4, c)
+SWDFT_FWD_DECL(8, r)
+SWDFT_FWD_DECL(8, c)
+SWDFT_FWD_DECL(16, r)
+SWDFT_FWD_DECL(16, c)
+SWDFT_FWD_DECL(32, r)
+SWDFT_FWD_DECL(32, c)
+#undef SWDFT_FWD_DECL
 
 }  // namespace swdft

@@ -199,3 +199,20 @@ def test_binding_rejects_bad_tensors(swd):
         p.exec_ptr(base.data_ptr() + 2, torch.empty(p.out_shape, dtype=torch.complex64,
                                                     device="cuda").data_ptr())
     assert e.value.name == "SWDFT_E_ALIGN"
+
+
+@pytest.mark.parametrize("n0,n1,kg", [(8, 1, 2), (8, 8, 2), (16, 16, 2), (16, 4, 2), (32, 8, 1),
+                                      (32, 32, 1), (32, 2, 2), (16, 32, 2)],
+                         ids=lambda v: str(v))
+def test_tree_split_streams(swd, orc, n0, n1, kg):
+    """Column streams split over kg lanes by k0 residue (per-lane twiddle
+    rotation) must give the same transform as unsplit streams."""
+    import os
+    N0, N1 = 2 * n0 + 45, 3 * (64 // n1) + n1 + 1
+    x = workloads.normal_complex((N0, N1), seed=n0 * 7 + n1 + kg)
+    os.environ["SWDFT_TREE_KG"] = str(kg)
+    try:
+        y = gpu_full(swd, x, n0, n1)
+    finally:
+        del os.environ["SWDFT_TREE_KG"]
+    assert rel_err(y, orc.swdft2d(x.astype(np.complex128), n0, n1)) <= TOL_F32
