@@ -279,20 +279,38 @@ def run_cplx2048(args, swd, dev) -> dict:
     log(f"tree: {avg_ms * 1e3:.1f} us/launch, {rf['achieved']:.0f} GB/s")
     q0, q1 = workloads.window_sample(P0, P1, 4096, 2003)
     got = sampled(y[0], q0, q1)
+    # the dense matrix-core variant on the same input and output buffer
+    pd = swd.Plan(N0, N1, n0, n1, torch.complex64, batch=1, algo="dense_bf16x2")
+    log(pd.describe())
+    for _ in range(args.warmup):
+        pd.forward(x, out=y)
+    torch.cuda.synchronize()
+    d_ms, d_wall, _ = time_launches(lambda: pd.forward(x, out=y), args.steps, stream)
+    got_d = sampled(y[0], q0, q1)
+    # real flops of the three split products: 8 n0 n1 (n0 + n1) per window, times 3
+    d_flops = 3 * 8 * n0 * n1 * (n0 + n1) * P0 * P1
+    dense = {"algo": "dense_bf16x2", "value": coeffs / (d_wall / args.steps), "unit": "coeffs/s",
+             "avg_launch_us": d_ms * 1e3,
+             "roofline": roofline(alg_bytes, d_ms, "dense_fwd_kernel<32,8,complex>"),
+             "mfma_tflops": d_flops / (d_ms * 1e-3) / 1e12, "mfma_peak_tflops": 2500.0}
+    log(f"dense: {d_ms * 1e3:.1f} us/launch")
     del y
     cpu, err = None, None
     if not args.no_cpu_baseline:
         import oracle
         orc = oracle.get()
         xd = x_np.astype(np.complex128)
-        err = rel(got, orc.swdft2d(xd, n0, n1, windows=(q0, q1)))
+        ref = orc.swdft2d(xd, n0, n1, windows=(q0, q1))
+        err = rel(got, ref)
+        dense["rel_err"] = rel(got_d, ref)
+        dense["max_abs_err"] = float(np.max(np.abs(got_d - ref)))
         cpu = oracle_rate(orc, xd, n0, n1, P0, P1, args.cpu_seconds, 3003)
     out = base_record(args, coeffs / step_s, step_s * 1e3, "f32", {
         "workload": "cplx2048: one 2048x512 complex64 image (re, im N(0,1)), 32x8 windows -> "
                     "2017x505x256 complex64 coefficients",
         "N0": N0, "N1": N1, "n0": n0, "n1": n1, "batch": 1, "algo": "tree",
         "coeffs_per_step": coeffs})
-    out.update({"roofline": rf, "rel_err": err, "cpu_baseline": cpu})
+    out.update({"roofline": rf, "rel_err": err, "dense": dense, "cpu_baseline": cpu})
     return out
 
 

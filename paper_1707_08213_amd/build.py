@@ -14,7 +14,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIBRARY = os.path.join(PKG, "libswdft2d.so")
-SOURCES = ["abi.hip", "tree_fwd.hip", "tree_adj.hip", "direct_f64.hip"] + [
+SOURCES = ["abi.hip", "tree_fwd.hip", "tree_adj.hip", "direct_f64.hip", "dense_mfma.hip",
+           "dense_mfma_r.hip", "dense_mfma_c.hip"] + [
     f"tree_{kind}_n{n}_{t}.hip" for kind in ("fwd", "adj") for n in (1, 2, 4, 8, 16, 32)
     for t in ("r", "c")]
 

@@ -233,6 +233,34 @@ swdft_status_t ensure_workspace(swdft2d_plan_s* p, size_t bytes) {
   return SWDFT_OK;
 }
 
+// Window rows per wave of the dense kernel: a multiple of 16 (one row chunk),
+// enough waves to fill the chip, and long enough that the row products
+// recomputed at each slab top (n0 - 1 rows, rounded to 16) stay small.
+swdft::DenseGeom dense_geom(const swdft2d_plan_s* p) {
+  swdft::DenseGeom g{};
+  g.N0 = p->N0;
+  g.N1 = p->N1;
+  g.P0 = p->P0;
+  g.P1 = p->P1;
+  g.x_image_stride = p->N0 * p->N1;
+  g.y_image_stride = p->P0 * p->P1 * p->n0 * p->n1;
+  g.nstrips = (int32_t)ceil_div(p->P1, swdft::dense_columns_per_wave(p->n0, p->n1));
+  int64_t S = 0;
+  const char* env = std::getenv("SWDFT_DENSE_SLAB");
+  if (env) S = std::atoll(env);
+  if (S <= 0) {
+    S = ceil_div(p->P0 * g.nstrips * p->batch, 4096);
+    S = std::max<int64_t>(S, 64);
+  }
+  S = ceil_div(std::max<int64_t>(S, 16), 16) * 16;
+  S = std::min<int64_t>(S, ceil_div(p->P0, 16) * 16);
+  g.S = (int32_t)S;
+  g.nslabs = (int32_t)ceil_div(p->P0, g.S);
+  g.batch = (int32_t)p->batch;
+  g.scale = p->norm == SWDFT_NORM_ORTHO ? (float)(1.0 / std::sqrt((double)p->n0 * p->n1)) : 1.0f;
+  return g;
+}
+
 swdft::DirectGeom direct_geom(const swdft2d_plan_s* p) {
   swdft::DirectGeom g{};
   g.N0 = p->N0;
@@ -341,8 +369,9 @@ swdft_status_t swdft2d_set_algo(swdft2d_plan_t plan, swdft_algo_t algo) {
       if (f64_dtype(plan->dtype))
         return fail(SWDFT_E_DTYPE, "algorithm %d computes in FP32 and needs an R32/C32 plan",
                     (int)algo);
-      if (algo == SWDFT_ALGO_DENSE_BF16X2)
-        return fail(SWDFT_E_DTYPE, "the dense BF16x2 algorithm is not available in this build");
+      if (algo == SWDFT_ALGO_DENSE_BF16X2 && !swdft::dense_supported(plan->n0, plan->n1))
+        return fail(SWDFT_E_WINDOW, "the dense BF16x2 algorithm supports n0, n1 in {8, 16, 32}, "
+                    "not %d x %d", plan->n0, plan->n1);
       break;
     case SWDFT_ALGO_DIRECT_F64:
       if (!f64_dtype(plan->dtype))
@@ -368,6 +397,10 @@ swdft_status_t swdft2d_exec(swdft2d_plan_t plan, const void* x, void* y, hipStre
     case SWDFT_ALGO_TREE:
       e = swdft::launch_tree_fwd(p->n0, p->n1, real_dtype(p->dtype), x,
                                  static_cast<float2*>(y), tree_geom(p), p->tw32, stream);
+      break;
+    case SWDFT_ALGO_DENSE_BF16X2:
+      e = swdft::launch_dense_fwd(p->n0, p->n1, real_dtype(p->dtype), x, static_cast<float2*>(y),
+                                  dense_geom(p), p->tw32, stream);
       break;
     case SWDFT_ALGO_DIRECT_F64:
       e = swdft::launch_direct_f64(p->n0, p->n1, real_dtype(p->dtype), x,
@@ -447,6 +480,14 @@ swdft_status_t swdft2d_describe(swdft2d_plan_t plan, char* buf, int32_t len) {
              p->n0, p->n1, (long long)p->N0, (long long)p->N1, (long long)p->batch, g.kg,
              swdft::tree_fwd_columns_per_wave(p->n0, p->n1, g.kg),
              swdft::tree_fwd_rows_per_chunk(p->n0, p->n1, g.kg), g.S, g.nstrips, g.nslabs,
+             (long long)g.nstrips * g.nslabs * p->batch);
+  } else if (a == SWDFT_ALGO_DENSE_BF16X2) {
+    const swdft::DenseGeom g = dense_geom(p);
+    snprintf(buf, (size_t)len,
+             "algo=dense_bf16x2 n=%dx%d N=%lldx%lld batch=%lld cols_per_wave=%d slab=%d strips=%d "
+             "slabs=%d waves=%lld",
+             p->n0, p->n1, (long long)p->N0, (long long)p->N1, (long long)p->batch,
+             swdft::dense_columns_per_wave(p->n0, p->n1), g.S, g.nstrips, g.nslabs,
              (long long)g.nstrips * g.nslabs * p->batch);
   } else {
     snprintf(buf, (size_t)len, "algo=direct_f64 n=%dx%d N=%lldx%lld batch=%lld windows_per_block=%d",

@@ -50,6 +50,19 @@ struct AdjGeom {
   float scale;
 };
 
+// Geometry of one dense (matrix-core) launch: one wave owns 16/n1 window
+// columns (one when n1 >= 16) and a slab of S window rows (S a multiple of 16).
+struct DenseGeom {
+  int64_t N0, N1, P0, P1;
+  int64_t x_image_stride;
+  int64_t y_image_stride;
+  int32_t S;
+  int32_t nstrips;
+  int32_t nslabs;
+  int32_t batch;
+  float scale;
+};
+
 struct DirectGeom {
   int64_t N0, N1, P0, P1;
   int64_t x_image_stride;
@@ -76,6 +89,11 @@ int tree_adj_rows_per_chunk(int n0, int n1);
 int tree_adj_columns_per_wave(int n0, int n1);
 // workspace elements (float for real input, float2 for complex) of one adjoint launch
 int64_t tree_adj_workspace_elems(int n0, int n1, const AdjGeom& g);
+
+hipError_t launch_dense_fwd(int n0, int n1, bool real_input, const void* x, float2* y,
+                            const DenseGeom& g, const TwiddlesF32& tw, hipStream_t stream);
+bool dense_supported(int n0, int n1);
+int dense_columns_per_wave(int n0, int n1);
 
 hipError_t launch_direct_f64(int n0, int n1, bool real_input, const void* x, double2* y,
                              const DirectGeom& g, const TwiddlesF64& tw, hipStream_t stream);
