@@ -135,7 +135,8 @@ swdft_status_t swdft2d_backward(swdft2d_plan_t plan, const void* dy, void* dx, h
  * make sure no work enqueued with the plan is still running. */
 swdft_status_t swdft2d_destroy(swdft2d_plan_t plan);
 
-/* batch*P0*P1*n0*n1, or -1 for a null plan. */
+/* batch*P0*P1*n0*n1 (sum over images for a batched plan), or -1 for a null
+ * plan. */
 int64_t swdft2d_output_elems(swdft2d_plan_t plan);
 
 /* Byte size of y (output_elems times 8 or 16), or -1 for a null plan. */
@@ -150,6 +151,44 @@ const char* swdft2d_status_string(swdft_status_t status);
 
 /* Detail of the last failing call on the calling thread ("" if none). */
 const char* swdft2d_last_error(void);
+
+/* One image of a batched plan. Offsets count elements of the caller's packed
+ * x (of the plan's dtype) and complex elements of the packed y; image i's
+ * input is x[x_offset .. x_offset + N0*N1) row-major and its output is
+ * y[y_offset .. y_offset + P0*P1*n0*n1) in the layout of a single-image plan.
+ * Output ranges of different images must not overlap. */
+typedef struct {
+    int64_t N0, N1;     /* image size */
+    int32_t n0, n1;     /* window size, each in {8, 16, 32} */
+    int64_t x_offset;   /* elements of x before this image */
+    int64_t y_offset;   /* complex elements of y before this image */
+} swdft2d_desc_t;
+
+/* Plan for `count` images of uneven sizes and window shapes, transformed by
+ * one exec. dtype must be R32 or C32 (E_DTYPE otherwise). Checks each
+ * descriptor as swdft2d_plan does (E_ARG, E_NOT_POW2, E_WINDOW), rejects
+ * window sizes outside {8,16,32} (E_WINDOW), negative offsets and overlapping
+ * output ranges (E_ARG), and sizes that overflow int64 (E_OVERFLOW). Images
+ * are grouped by window shape; each group runs its own persistent kernel (a
+ * grid of the waves the chip keeps resident pulling tiles from a work list
+ * sorted by decreasing output bytes). At the first exec the plan uploads its
+ * work tables (hipMalloc, owned by the plan) and builds a graph of a
+ * counter-reset kernel followed by the group kernels; each exec is one
+ * hipGraphLaunch on the stream. Exec with other x/y pointers rebinds the
+ * graph's arguments. backward is not available (E_PLAN). Touches no GPU. */
+swdft_status_t swdft2d_plan_batched(swdft2d_plan_t* out, const swdft2d_desc_t* descs, int64_t count,
+                                    swdft_dtype_t dtype);
+
+/* Time candidate configurations on the caller's x and y and keep the fastest:
+ * tree tile shapes (lanes per column stream, slab length) and, when the
+ * plan's algorithm is AUTO (or DENSE_BF16X2) and the window shape allows, the
+ * dense matrix-core variant, which is admitted only if its output agrees with
+ * the tree's to a normwise relative difference of 1e-5. Batched plans are
+ * tuned per window-shape group. y is overwritten. Blocks until the stream is
+ * idle. Results are appended to the file named by SWDFT_AUTOTUNE_CACHE (one
+ * JSON object per line) when it is set; plans read that file at their first
+ * exec. R64/C64 plans have nothing to tune (returns SWDFT_OK). */
+swdft_status_t swdft2d_tune(swdft2d_plan_t plan, const void* x, void* y, hipStream_t stream);
 
 /* Measurement aid (not part of the transform): fill `bytes` bytes at y
  * (8-byte aligned, bytes a multiple of 8) with a constant using the same

@@ -20,8 +20,8 @@ import torch
 from . import _lib
 from ._lib import SwdftError, check, lib
 
-__all__ = ["Plan", "swdft2d", "swdft2d_backward", "SWDFT2dFn", "write_probe", "SwdftError",
-           "output_shape"]
+__all__ = ["Plan", "BatchedPlan", "swdft2d", "swdft2d_batched", "swdft2d_backward", "SWDFT2dFn",
+           "write_probe", "SwdftError", "output_shape"]
 
 _DTYPES = {
     torch.float32: _lib.SWDFT_R32, torch.complex64: _lib.SWDFT_C32,
@@ -118,6 +118,17 @@ class Plan:
             self.backward_ptr(dy.data_ptr(), out.data_ptr(), stream)
         return out
 
+    def tune(self, x: torch.Tensor, out: torch.Tensor | None = None) -> None:
+        """Time candidate tile shapes / algorithms on x and keep the fastest
+        (overwrites `out`; blocks until done)."""
+        self._check_x(x)
+        if out is None:
+            out = torch.empty(self.out_shape, dtype=self.out_dtype, device=x.device)
+        with torch.cuda.device(x.device):
+            stream = torch.cuda.current_stream(x.device).cuda_stream
+            check(lib.swdft2d_tune(self.handle, x.data_ptr(), out.data_ptr(), stream),
+                  "swdft2d_tune")
+
     def close(self):
         if getattr(self, "handle", None) is not None:
             check(lib.swdft2d_destroy(self.handle), "swdft2d_destroy")
@@ -128,6 +139,111 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class BatchedPlan:
+    """Many images of uneven sizes and window shapes in one exec.
+
+    shapes: list of (N0, N1, n0, n1) with n0, n1 in {8, 16, 32}. Inputs are
+    packed into one flat tensor (image i at x_offsets[i], row-major) and so
+    are outputs (image i's [P0, P1, n0, n1] block at y_offsets[i])."""
+
+    def __init__(self, shapes, dtype=torch.float32, norm="none", algo="auto"):
+        if dtype not in (torch.float32, torch.complex64):
+            raise TypeError("batched plans take float32 or complex64 input")
+        self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        self.dtype = dtype
+        self.code = _DTYPES[dtype]
+        self.x_offsets, self.y_offsets, self.out_shapes = [], [], []
+        xo = yo = 0
+        descs = (_lib.Desc * len(self.shapes))()
+        for i, (N0, N1, n0, n1) in enumerate(self.shapes):
+            P0, P1 = N0 - n0 + 1, N1 - n1 + 1
+            descs[i] = _lib.Desc(N0, N1, n0, n1, xo, yo)
+            self.x_offsets.append(xo)
+            self.y_offsets.append(yo)
+            self.out_shapes.append((P0, P1, n0, n1))
+            xo += N0 * N1
+            yo += max(P0, 0) * max(P1, 0) * n0 * n1
+        self.x_numel, self.y_numel = xo, yo
+        h = ctypes.c_void_p()
+        check(lib.swdft2d_plan_batched(ctypes.byref(h), ctypes.cast(descs, ctypes.c_void_p),
+                                       len(self.shapes), self.code), "swdft2d_plan_batched")
+        self.handle = h
+        try:
+            check(lib.swdft2d_set_norm(h, _NORMS[norm]), "swdft2d_set_norm")
+            check(lib.swdft2d_set_algo(h, _ALGOS[algo]), "swdft2d_set_algo")
+        except Exception:
+            lib.swdft2d_destroy(h)
+            self.handle = None
+            raise
+
+    def pack(self, images, device=None) -> torch.Tensor:
+        """Concatenate images (each [N0, N1]) into the packed input layout."""
+        flat = [im.reshape(-1) for im in images]
+        x = torch.cat(flat).to(device=device if device is not None else flat[0].device)
+        return x.to(self.dtype).contiguous()
+
+    def unpack(self, y: torch.Tensor):
+        """Views of the packed output, one [P0, P1, n0, n1] tensor per image."""
+        out = []
+        for off, shp in zip(self.y_offsets, self.out_shapes):
+            n = shp[0] * shp[1] * shp[2] * shp[3]
+            out.append(y[off:off + n].view(shp))
+        return out
+
+    def output_elems(self) -> int:
+        return int(lib.swdft2d_output_elems(self.handle))
+
+    def describe(self) -> str:
+        buf = ctypes.create_string_buffer(4096)
+        check(lib.swdft2d_describe(self.handle, buf, 4096), "swdft2d_describe")
+        return buf.value.decode()
+
+    def _check(self, x, out):
+        if x.dtype != self.dtype or not x.is_cuda or not x.is_contiguous() or x.numel() != self.x_numel:
+            raise ValueError(f"x must be a contiguous cuda {self.dtype} tensor of {self.x_numel} elements")
+        if out is None:
+            out = torch.empty(self.y_numel, dtype=torch.complex64, device=x.device)
+        elif out.dtype != torch.complex64 or out.numel() != self.y_numel or not out.is_contiguous():
+            raise ValueError("out has the wrong size or dtype")
+        return out
+
+    def forward(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        out = self._check(x, out)
+        with torch.cuda.device(x.device):
+            stream = torch.cuda.current_stream(x.device).cuda_stream
+            check(lib.swdft2d_exec(self.handle, x.data_ptr(), out.data_ptr(), stream),
+                  "swdft2d_exec")
+        return out
+
+    def tune(self, x: torch.Tensor, out: torch.Tensor | None = None) -> None:
+        out = self._check(x, out)
+        with torch.cuda.device(x.device):
+            stream = torch.cuda.current_stream(x.device).cuda_stream
+            check(lib.swdft2d_tune(self.handle, x.data_ptr(), out.data_ptr(), stream),
+                  "swdft2d_tune")
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            check(lib.swdft2d_destroy(self.handle), "swdft2d_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def swdft2d_batched(images, windows, norm: str = "none", algo: str = "auto"):
+    """Transform a list of 2D images (float32 or complex64, on one cuda device)
+    with per-image windows [(n0, n1), ...] in one exec; returns a list of
+    [P0, P1, n0, n1] complex64 tensors (views of one packed buffer)."""
+    shapes = [(im.shape[0], im.shape[1], w[0], w[1]) for im, w in zip(images, windows)]
+    plan = BatchedPlan(shapes, dtype=images[0].dtype, norm=norm, algo=algo)
+    y = plan.forward(plan.pack(images))
+    return plan.unpack(y)
 
 
 _cache_lock = threading.Lock()

@@ -24,6 +24,12 @@ STATUS = {
 STATUS_CODE = {v: k for k, v in STATUS.items()}
 MAX_WINDOW = 32
 
+class Desc(ctypes.Structure):
+    """swdft2d_desc_t"""
+    _fields_ = [("N0", ctypes.c_int64), ("N1", ctypes.c_int64), ("n0", ctypes.c_int32),
+                ("n1", ctypes.c_int32), ("x_offset", ctypes.c_int64), ("y_offset", ctypes.c_int64)]
+
+
 # name -> (restype, argtypes), the full exported surface
 _i64, _i32, _vp, _int = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int
 _PLAN_P = ctypes.POINTER(ctypes.c_void_p)
@@ -40,6 +46,8 @@ SIGNATURES = {
     "swdft2d_status_string": (ctypes.c_char_p, [_int]),
     "swdft2d_last_error": (ctypes.c_char_p, []),
     "swdft2d_write_probe": (_int, [_vp, _i64, _vp]),
+    "swdft2d_plan_batched": (_int, [_PLAN_P, _vp, _i64, _int]),
+    "swdft2d_tune": (_int, [_vp, _vp, _vp, _vp]),
 }
 
 

@@ -1,6 +1,7 @@
 """Compile libswdft2d.so (the HIP kernels and the C ABI) for gfx950 in-tree.
 
-Usage: python -m paper_1707_08213_amd.build [-v]
+Usage: python paper_1707_08213_amd/build.py [-v]   (run as a script: importing the
+package would load the library this builds)
 """
 from __future__ import annotations
 
@@ -14,8 +15,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIBRARY = os.path.join(PKG, "libswdft2d.so")
-SOURCES = ["abi.hip", "tree_fwd.hip", "tree_adj.hip", "direct_f64.hip", "dense_mfma.hip",
-           "dense_mfma_r.hip", "dense_mfma_c.hip"] + [
+SOURCES = ["abi.hip", "batched_host.hip", "tune.hip", "tree_fwd.hip", "tree_adj.hip", "direct_f64.hip", "dense_mfma.hip",
+           "dense_mfma_r.hip", "dense_mfma_c.hip", "batched.hip", "batched_tree_r.hip",
+           "batched_tree_c.hip", "batched_dense_r.hip", "batched_dense_c.hip"] + [
     f"tree_{kind}_n{n}_{t}.hip" for kind in ("fwd", "adj") for n in (1, 2, 4, 8, 16, 32)
     for t in ("r", "c")]
 
@@ -47,8 +49,12 @@ def _compile(src: str, verbose: bool) -> str:
 def build(verbose: bool = False, jobs: int = 8) -> str:
     os.makedirs(BUILD, exist_ok=True)
     # the largest window instantiations take longest: start them first
-    order = sorted(SOURCES, key=lambda s: -max([int(t[1:]) for t in s[:-4].split("_")
-                                                 if t[:1] == "n" and t[1:].isdigit()] or [0]))
+    def cost(src):
+        if src.startswith("batched_"):
+            return 100
+        return max([int(t[1:]) for t in src[:-4].split("_") if t[:1] == "n" and t[1:].isdigit()]
+                   or [0])
+    order = sorted(SOURCES, key=lambda s: -cost(s))
     with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), order))
     tmp = LIBRARY + ".tmp"

@@ -13,28 +13,13 @@
 #include <string>
 #include <unordered_set>
 
-#include "internal.h"
-#include "swdft2d.h"
+#include "plan.h"
 
 using swdft::TwiddlesF32;
 using swdft::TwiddlesF64;
 
-struct swdft2d_plan_s {
-  int64_t N0 = 0, N1 = 0, P0 = 0, P1 = 0, batch = 0;
-  int32_t n0 = 0, n1 = 0;
-  swdft_dtype_t dtype = SWDFT_R32;
-  swdft_norm_t norm = SWDFT_NORM_NONE;
-  swdft_algo_t algo = SWDFT_ALGO_AUTO;
-  int32_t tree_slab = 0;  // 0 = choose automatically
-  int32_t tree_kg = 0;    // 0 = choose automatically
-  TwiddlesF32 tw32{};
-  TwiddlesF64 tw64{};
-  void* workspace = nullptr;
-  size_t workspace_bytes = 0;
-  int workspace_device = -1;
-};
-
-namespace {
+namespace swdft {
+namespace host {
 
 thread_local std::string g_last_error;
 
@@ -61,6 +46,11 @@ swdft_status_t device_fail(hipError_t e, const char* what) {
 bool is_live(swdft2d_plan_t p) {
   std::lock_guard<std::mutex> lk(g_plans_mutex);
   return p != nullptr && live_plans().count(p) != 0;
+}
+
+void register_plan(swdft2d_plan_s* p) {
+  std::lock_guard<std::mutex> lk(g_plans_mutex);
+  live_plans().insert(p);
 }
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
@@ -107,8 +97,20 @@ void make_twiddles(int n, double2* w) {
   for (int m = half; m < n; ++m) w[m] = make_double2(-w[m - half].x, -w[m - half].y);
 }
 
+// FP64 twiddles rounded once (round to nearest even) to FP32.
+void make_twiddles_f32(int n, float2* w) {
+  double2 d[kMaxWindow];
+  make_twiddles(n, d);
+  for (int m = 0; m < n; ++m) w[m] = make_float2((float)d[m].x, (float)d[m].y);
+}
+
+float norm_scale(swdft_norm_t norm, int n0, int n1) {
+  return norm == SWDFT_NORM_ORTHO ? (float)(1.0 / std::sqrt((double)n0 * n1)) : 1.0f;
+}
+
 swdft_algo_t resolve_algo(const swdft2d_plan_s* p) {
   if (p->algo != SWDFT_ALGO_AUTO) return p->algo;
+  if (p->tuned_algo != SWDFT_ALGO_AUTO) return p->tuned_algo;
   return f64_dtype(p->dtype) ? SWDFT_ALGO_DIRECT_F64 : SWDFT_ALGO_TREE;
 }
 
@@ -160,7 +162,7 @@ swdft::TreeGeom tree_geom(const swdft2d_plan_s* p) {
   g.nstrips = (int32_t)ceil_div(p->P1, swdft::tree_fwd_columns_per_wave(p->n0, p->n1, g.kg));
   g.nslabs = (int32_t)ceil_div(p->P0, g.S);
   g.batch = (int32_t)p->batch;
-  g.scale = p->norm == SWDFT_NORM_ORTHO ? (float)(1.0 / std::sqrt((double)p->n0 * p->n1)) : 1.0f;
+  g.scale = norm_scale(p->norm, p->n0, p->n1);
   return g;
 }
 
@@ -245,9 +247,11 @@ swdft::DenseGeom dense_geom(const swdft2d_plan_s* p) {
   g.x_image_stride = p->N0 * p->N1;
   g.y_image_stride = p->P0 * p->P1 * p->n0 * p->n1;
   g.nstrips = (int32_t)ceil_div(p->P1, swdft::dense_columns_per_wave(p->n0, p->n1));
-  int64_t S = 0;
-  const char* env = std::getenv("SWDFT_DENSE_SLAB");
-  if (env) S = std::atoll(env);
+  int64_t S = p->dense_slab;
+  if (S <= 0) {
+    const char* env = std::getenv("SWDFT_DENSE_SLAB");
+    if (env) S = std::atoll(env);
+  }
   if (S <= 0) {
     S = ceil_div(p->P0 * g.nstrips * p->batch, 4096);
     S = std::max<int64_t>(S, 64);
@@ -297,7 +301,10 @@ swdft_status_t check_buffers(const swdft2d_plan_s* p, const void* in, int64_t in
   return SWDFT_OK;
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace swdft
+
+using namespace swdft::host;
 
 extern "C" {
 
@@ -340,14 +347,9 @@ swdft_status_t swdft2d_plan(swdft2d_plan_t* out, int64_t N0, int64_t N1, int32_t
   p->dtype = dtype;
   make_twiddles(n0, p->tw64.w0);
   make_twiddles(n1, p->tw64.w1);
-  for (int m = 0; m < n0; ++m)
-    p->tw32.w0[m] = make_float2((float)p->tw64.w0[m].x, (float)p->tw64.w0[m].y);
-  for (int m = 0; m < n1; ++m)
-    p->tw32.w1[m] = make_float2((float)p->tw64.w1[m].x, (float)p->tw64.w1[m].y);
-  {
-    std::lock_guard<std::mutex> lk(g_plans_mutex);
-    live_plans().insert(p);
-  }
+  make_twiddles_f32(n0, p->tw32.w0);
+  make_twiddles_f32(n1, p->tw32.w1);
+  register_plan(p);
   *out = p;
   return SWDFT_OK;
 }
@@ -357,11 +359,22 @@ swdft_status_t swdft2d_set_norm(swdft2d_plan_t plan, swdft_norm_t norm) {
   if (norm != SWDFT_NORM_NONE && norm != SWDFT_NORM_ORTHO)
     return fail(SWDFT_E_ARG, "unknown norm %d", (int)norm);
   plan->norm = norm;
+  if (plan->bs) batched_build_tables(plan);
   return SWDFT_OK;
 }
 
 swdft_status_t swdft2d_set_algo(swdft2d_plan_t plan, swdft_algo_t algo) {
   if (!is_live(plan)) return fail(SWDFT_E_PLAN, "null or destroyed plan");
+  if (plan->kind == 1) {
+    if (algo != SWDFT_ALGO_AUTO && algo != SWDFT_ALGO_TREE && algo != SWDFT_ALGO_DENSE_BF16X2)
+      return fail((int)algo == SWDFT_ALGO_DIRECT_F64 ? SWDFT_E_DTYPE : SWDFT_E_ARG,
+                  "batched plans run the tree or the dense variant");
+    plan->algo = algo;
+    if (algo != SWDFT_ALGO_AUTO)
+      for (auto& kv : plan->bs->cfg) kv.second.dense = (algo == SWDFT_ALGO_DENSE_BF16X2);
+    batched_build_tables(plan);
+    return SWDFT_OK;
+  }
   switch (algo) {
     case SWDFT_ALGO_AUTO: break;
     case SWDFT_ALGO_TREE:
@@ -386,6 +399,8 @@ swdft_status_t swdft2d_set_algo(swdft2d_plan_t plan, swdft_algo_t algo) {
 
 swdft_status_t swdft2d_exec(swdft2d_plan_t plan, const void* x, void* y, hipStream_t stream) {
   if (!is_live(plan)) return fail(SWDFT_E_PLAN, "null or destroyed plan");
+  if (plan->kind == 1) return batched_exec(plan, x, y, stream);
+  if (!plan->tuned) apply_cached_tuning(plan);
   const swdft2d_plan_s* p = plan;
   const int64_t xb = p->batch * p->N0 * p->N1 * x_elem_bytes(p->dtype);
   const int64_t yb = swdft2d_output_bytes(plan);
@@ -415,6 +430,7 @@ swdft_status_t swdft2d_exec(swdft2d_plan_t plan, const void* x, void* y, hipStre
 
 swdft_status_t swdft2d_backward(swdft2d_plan_t plan, const void* dy, void* dx, hipStream_t stream) {
   if (!is_live(plan)) return fail(SWDFT_E_PLAN, "null or destroyed plan");
+  if (plan->kind == 1) return fail(SWDFT_E_PLAN, "backward is not available for batched plans");
   const swdft2d_plan_s* p = plan;
   const int64_t xb = p->batch * p->N0 * p->N1 * x_elem_bytes(p->dtype);
   const int64_t yb = swdft2d_output_bytes(plan);
@@ -453,12 +469,17 @@ swdft_status_t swdft2d_destroy(swdft2d_plan_t plan) {
     if (cur >= 0) (void)hipSetDevice(cur);
     if (e != hipSuccess) st = device_fail(e, "workspace free");
   }
+  if (plan->bs) {
+    batched_free(plan->bs);
+    delete plan->bs;
+  }
   delete plan;
   return st;
 }
 
 int64_t swdft2d_output_elems(swdft2d_plan_t plan) {
   if (!is_live(plan)) return -1;
+  if (plan->kind == 1) return plan->bs->out_elems;
   return plan->batch * plan->P0 * plan->P1 * plan->n0 * plan->n1;
 }
 
@@ -471,6 +492,16 @@ swdft_status_t swdft2d_describe(swdft2d_plan_t plan, char* buf, int32_t len) {
   if (!is_live(plan)) return fail(SWDFT_E_PLAN, "null or destroyed plan");
   if (!buf || len < 1) return fail(SWDFT_E_ARG, "describe buffer is null or empty");
   const swdft2d_plan_s* p = plan;
+  if (p->kind == 1) {
+    const swdft::BatchState* bs = p->bs;
+    std::string d = "kind=batched images=" + std::to_string(bs->descs.size()) +
+                    " items=" + std::to_string(bs->items.size()) + " classes=";
+    for (const auto& c : bs->classes)
+      d += std::to_string(c.n0) + "x" + std::to_string(c.n1) + (c.dense ? ":dense" : ":tree") +
+           "/" + std::to_string(c.item_count) + " ";
+    snprintf(buf, (size_t)len, "%s", d.c_str());
+    return SWDFT_OK;
+  }
   const swdft_algo_t a = resolve_algo(p);
   if (a == SWDFT_ALGO_TREE) {
     const swdft::TreeGeom g = tree_geom(p);

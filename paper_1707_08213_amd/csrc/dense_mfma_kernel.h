@@ -116,26 +116,39 @@ struct DenseCfg {
   static constexpr int RL = N0W > 16 ? 64 : 32;            // LDS ring rows
   static constexpr int RLP = RL + 16;                      // + 8 guard each side
   static constexpr int LOOK = (N0W - 1 + 15) / 16;         // row chunks ahead of windows
+  static constexpr int LDS_BF16 = 2 * 2 * NC * RLP;
   static_assert(N0W >= 8 && N1W >= 8, "dense path needs n0, n1 >= 8");
   static_assert(16 * (LOOK + 1) <= RL, "ring too short");
 };
 
 template <int N0W, int N1W, bool REAL>
-__global__ __launch_bounds__(64) void dense_fwd_kernel(const void* __restrict__ xv,
-                                                       float2* __restrict__ y, DenseGeom g,
-                                                       TwiddlesF32 tw) {
+__device__ __forceinline__ __bf16* zslot(__bf16* zr, int ri, int hl, int c, int e) {
   using C = DenseCfg<N0W, N1W, REAL>;
-  // Z ring: [re/im][hi/lo][column][8 + row slot (+ mirror of slots 0..7)]
-  __shared__ __attribute__((aligned(16))) __bf16 zr[2][2][C::NC][C::RLP];
+  return zr + (((ri * 2 + hl) * C::NC + c) * C::RLP + e);
+}
 
+// One tile of the dense variant: window columns [strip*QW, +QW) and window
+// rows [slab*S, +S) of image b. zr is the wave's LDS ring of
+// DenseCfg::LDS_BF16 elements (16-byte aligned).
+template <int N0W, int N1W, bool REAL>
+__device__ __forceinline__ void dense_fwd_tile(const void* __restrict__ xv, float2* __restrict__ y,
+                                               const DenseGeom& g_in, const float2* __restrict__ w0,
+                                               const float2* __restrict__ w1, int strip, int slab,
+                                               int b, __bf16* __restrict__ zr) {
+  using C = DenseCfg<N0W, N1W, REAL>;
   const int lane = threadIdx.x;
   const int l16 = lane & 15;
   const int lg = lane >> 4;
-  int id = blockIdx.x;
-  const int strip = id % g.nstrips;
-  id /= g.nstrips;
-  const int slab = id % g.nslabs;
-  const int b = id / g.nslabs;
+  DenseGeom g;
+  {
+    struct Words { int w[sizeof(DenseGeom) / 4]; };
+    const Words in = __builtin_bit_cast(Words, g_in);
+    Words out;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(DenseGeom) / 4); ++i)
+      out.w[i] = __builtin_amdgcn_readfirstlane(in.w[i]);
+    g = __builtin_bit_cast(DenseGeom, out);
+  }
   const int64_t q1_0 = (int64_t)strip * C::QW;
   const int64_t Q = (int64_t)slab * g.S;                  // first window row (multiple of 16)
   const int64_t q0_end = min(Q + (int64_t)g.S, g.P0);
@@ -155,7 +168,7 @@ __global__ __launch_bounds__(64) void dense_fwd_kernel(const void* __restrict__ 
         float v = 0.f;
         if (kidx < C::K2) {
           const int ri = kidx / N0W, j0 = kidx % N0W;
-          const float2 w = tw.w0[(j0 * k0) & (N0W - 1)];
+          const float2 w = w0[(j0 * k0) & (N0W - 1)];
           v = ro == 0 ? (ri == 0 ? w.x : -w.y) : (ri == 0 ? w.y : w.x);
         }
         __bf16 h, l;
@@ -175,7 +188,7 @@ __global__ __launch_bounds__(64) void dense_fwd_kernel(const void* __restrict__ 
         float v = 0.f;
         if (kidx < C::K1) {
           const int ri = kidx / N1W, j1 = kidx % N1W;
-          const float2 w = tw.w1[(j1 * k1) & (N1W - 1)];
+          const float2 w = w1[(j1 * k1) & (N1W - 1)];
           v = ri == 0 ? (ro == 0 ? w.x : w.y) : (ro == 0 ? -w.y : w.x);
         }
         __bf16 h, l;
@@ -228,11 +241,11 @@ __global__ __launch_bounds__(64) void dense_fwd_kernel(const void* __restrict__ 
         uint2 ph, pl;
         __builtin_memcpy(&ph, hi, 8);
         __builtin_memcpy(&pl, lo, 8);
-        *reinterpret_cast<uint2*>(&zr[ro][0][c][8 + slot]) = ph;
-        *reinterpret_cast<uint2*>(&zr[ro][1][c][8 + slot]) = pl;
+        *reinterpret_cast<uint2*>(zslot<N0W, N1W, REAL>(zr, ro, 0, c, 8 + slot)) = ph;
+        *reinterpret_cast<uint2*>(zslot<N0W, N1W, REAL>(zr, ro, 1, c, 8 + slot)) = pl;
         if (slot < 8) {
-          *reinterpret_cast<uint2*>(&zr[ro][0][c][8 + C::RL + slot]) = ph;
-          *reinterpret_cast<uint2*>(&zr[ro][1][c][8 + C::RL + slot]) = pl;
+          *reinterpret_cast<uint2*>(zslot<N0W, N1W, REAL>(zr, ro, 0, c, 8 + C::RL + slot)) = ph;
+          *reinterpret_cast<uint2*>(zslot<N0W, N1W, REAL>(zr, ro, 1, c, 8 + C::RL + slot)) = pl;
         }
       });
     });
@@ -259,8 +272,8 @@ __global__ __launch_bounds__(64) void dense_fwd_kernel(const void* __restrict__ 
             const int ri = kbase / N0W, j0b = kbase % N0W;
             const int slot = (int)((wq + j0b) & (C::RL - 1)) + st;  // run start, mod RL below
             const int s = slot & (C::RL - 1);
-            bhi[KB] = load_run<(st & 7)>(&zr[ri][0][c][8 + s]);
-            blo[KB] = load_run<(st & 7)>(&zr[ri][1][c][8 + s]);
+            bhi[KB] = load_run<(st & 7)>(zslot<N0W, N1W, REAL>(zr, ri, 0, c, 8 + s));
+            blo[KB] = load_run<(st & 7)>(zslot<N0W, N1W, REAL>(zr, ri, 1, c, 8 + s));
           } else {
             bhi[KB] = bf16x8{};
             blo[KB] = bf16x8{};
@@ -286,6 +299,20 @@ __global__ __launch_bounds__(64) void dense_fwd_kernel(const void* __restrict__ 
     });
     __syncthreads();
   }
+}
+
+template <int N0W, int N1W, bool REAL>
+__global__ __launch_bounds__(64) void dense_fwd_kernel(const void* __restrict__ xv,
+                                                       float2* __restrict__ y, DenseGeom g,
+                                                       TwiddlesF32 tw) {
+  using C = DenseCfg<N0W, N1W, REAL>;
+  __shared__ __attribute__((aligned(16))) __bf16 zr[C::LDS_BF16];
+  int id = blockIdx.x;
+  const int strip = id % g.nstrips;
+  id /= g.nstrips;
+  const int slab = id % g.nslabs;
+  const int b = id / g.nslabs;
+  dense_fwd_tile<N0W, N1W, REAL>(xv, y, g, tw.w0, tw.w1, strip, slab, b, zr);
 }
 
 template <int N0W, int N1W, bool REAL>

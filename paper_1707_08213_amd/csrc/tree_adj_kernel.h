@@ -47,7 +47,7 @@ __device__ __forceinline__ float2 twmul_conj(float2 d, const float2* w) {
   } else if constexpr (4 * IDX == N) {
     return make_float2(-d.y, d.x);  // conj(-i) = i
   } else {
-    const float2 t = w[IDX];
+    const float2 t = uload(w + IDX);
     return make_float2(t.x * d.x + t.y * d.y, t.x * d.y - t.y * d.x);
   }
 }

@@ -55,6 +55,27 @@ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 
+// Load a value that is the same for every lane of the wave and keep it in
+// scalar registers. Used for twiddles and tile geometry, which the persistent
+// batched kernel reads from a device table at addresses the compiler cannot
+// prove unmodified (so it would otherwise hold them in vector registers).
+__device__ __forceinline__ float2 uload(const float2* p) {
+  const float2 v = *p;
+  return make_float2(__builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v.x))),
+                     __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v.y))));
+}
+
+template <typename T>
+__device__ __forceinline__ T uniform_copy(const T& src) {
+  static_assert(sizeof(T) % 4 == 0, "dword-sized");
+  struct Words { int w[sizeof(T) / 4]; };
+  const Words in = __builtin_bit_cast(Words, src);
+  Words out;
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) out.w[i] = __builtin_amdgcn_readfirstlane(in.w[i]);
+  return __builtin_bit_cast(T, out);
+}
+
 // d * Omega[IDX] for a length-N twiddle vector, IDX < N/2 known at compile
 // time. Omega[0] = 1 and Omega[N/4] = -i are applied exactly without a
 // multiply; every other value comes from the FP64-generated table.
@@ -65,7 +86,7 @@ __device__ __forceinline__ float2 twmul(float2 d, const float2* w) {
   } else if constexpr (4 * IDX == N) {
     return make_float2(d.y, -d.x);
   } else {
-    const float2 t = w[IDX];
+    const float2 t = uload(w + IDX);
     return make_float2(t.x * d.x - t.y * d.y, t.x * d.y + t.y * d.x);
   }
 }
@@ -197,24 +218,24 @@ struct TreeCfg {
   static constexpr int CR = R > RING ? R : RING;            // rows per chunk
   static constexpr int ZS = N1W + 1;                        // padded stride of one window column in LDS
   static constexpr int ZROW = QW * ZS;                      // float2 per chunk row in LDS
+  static constexpr int LDS_FLOAT2 = CR * ZROW;
   static_assert(KG == 1 || KG < N0W, "a split stream needs KG < n0");
   static_assert(N1W * KG <= 64, "one wave must hold a whole window column");
 };
 
+// One tile of the forward tree: window columns [strip*QW, +QW) and window
+// rows [slab*S, +S) of image b. w0, w1 point at the twiddle vectors (kernel
+// arguments or a device table); zl is the wave's LDS buffer of
+// TreeCfg::LDS_FLOAT2 elements.
 template <int N0W, int N1W, bool REAL, int KG>
-__global__ __launch_bounds__(64) void tree_fwd_kernel(const void* __restrict__ xv,
-                                                      float2* __restrict__ y, TreeGeom g,
-                                                      TwiddlesF32 tw) {
+__device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float2* __restrict__ y,
+                                              const TreeGeom& g_in, const float2* __restrict__ w0,
+                                              const float2* __restrict__ w1, int strip, int slab,
+                                              int b, float2* __restrict__ zl) {
   using C = TreeCfg<N0W, N1W, REAL, KG>;
   using CC = ColCfg<N0W, KG>;
-  __shared__ float2 zl[C::CR * C::ZROW];
-
   const int lane = threadIdx.x;
-  int id = xcd_tile(blockIdx.x, gridDim.x);
-  const int strip = id % g.nstrips;
-  id /= g.nstrips;
-  const int slab = id % g.nslabs;
-  const int b = id / g.nslabs;
+  const TreeGeom g = uniform_copy(g_in);
 
   const int64_t q1_0 = (int64_t)strip * C::QW;
   const int64_t row0 = (int64_t)slab * g.S;
@@ -245,7 +266,7 @@ __global__ __launch_bounds__(64) void tree_fwd_kernel(const void* __restrict__ x
     constexpr int u = U;
     if constexpr (KG > 1) {
       const int idx = (cp_res & ((1 << u) - 1)) * (N0W >> u);
-      lanefac[u] = tw.w0[idx];
+      lanefac[u] = w0[idx];
     } else {
       lanefac[u] = make_float2(1.f, 0.f);
     }
@@ -273,7 +294,7 @@ __global__ __launch_bounds__(64) void tree_fwd_kernel(const void* __restrict__ x
           v[d] = ok ? xc[row * g.N1 + col] : make_float2(0.f, 0.f);
         }
       });
-      row_levels<N1W>(v, tw.w1);
+      row_levels<N1W>(v, w1);
       if (g.scale != 1.0f) {
         sfor<0, N1W>([&](auto K) { v[K] = make_float2(v[K].x * g.scale, v[K].y * g.scale); });
       }
@@ -292,13 +313,27 @@ __global__ __launch_bounds__(64) void tree_fwd_kernel(const void* __restrict__ x
       if constexpr (N0W == 1) {
         if (store) store_nt(dst, z);
       } else {
-        column_levels<N0W, KG, st % C::RING>(z, ring, lanefac, tw.w0, [&](auto J, float2 v) {
+        column_levels<N0W, KG, st % C::RING>(z, ring, lanefac, w0, [&](auto J, float2 v) {
           if (store) store_nt(dst + (KG * J) * N1W, v);
         });
       }
     });
     __syncthreads();
   }
+}
+
+template <int N0W, int N1W, bool REAL, int KG>
+__global__ __launch_bounds__(64) void tree_fwd_kernel(const void* __restrict__ xv,
+                                                      float2* __restrict__ y, TreeGeom g,
+                                                      TwiddlesF32 tw) {
+  using C = TreeCfg<N0W, N1W, REAL, KG>;
+  __shared__ float2 zl[C::LDS_FLOAT2];
+  int id = xcd_tile(blockIdx.x, gridDim.x);
+  const int strip = id % g.nstrips;
+  id /= g.nstrips;
+  const int slab = id % g.nslabs;
+  const int b = id / g.nslabs;
+  tree_fwd_tile<N0W, N1W, REAL, KG>(xv, y, g, tw.w0, tw.w1, strip, slab, b, zl);
 }
 
 template <int N0W, int N1W, bool REAL>

@@ -152,3 +152,61 @@ def test_write_probe_checks():
     assert lib.swdft2d_write_probe(None, 64, None) == S["SWDFT_E_ARG"]
     assert lib.swdft2d_write_probe(0x10000, 12, None) == S["SWDFT_E_ARG"]
     assert lib.swdft2d_write_probe(0x10004, 16, None) == S["SWDFT_E_ALIGN"]
+
+
+def make_batched(shapes, dtype=_lib.SWDFT_R32, offsets=None):
+    descs = (_lib.Desc * len(shapes))()
+    xo = yo = 0
+    for i, (N0, N1, n0, n1) in enumerate(shapes):
+        if offsets is not None:
+            xo, yo = offsets[i]
+        descs[i] = _lib.Desc(N0, N1, n0, n1, xo, yo)
+        if offsets is None:
+            xo += N0 * N1
+            yo += (N0 - n0 + 1) * (N1 - n1 + 1) * n0 * n1
+    h = ctypes.c_void_p()
+    st = lib.swdft2d_plan_batched(ctypes.byref(h), ctypes.cast(descs, ctypes.c_void_p),
+                                  len(shapes), dtype)
+    return st, h
+
+
+def test_batched_plan_validation():
+    good = [(128, 256, 8, 8), (512, 128, 16, 16), (256, 256, 32, 32), (128, 512, 8, 32)]
+    st, h = make_batched(good)
+    assert st == 0, lib.swdft2d_last_error()
+    expect = sum((a - c + 1) * (b - d + 1) * c * d for a, b, c, d in good)
+    assert lib.swdft2d_output_elems(h) == expect
+    buf = ctypes.create_string_buffer(1024)
+    assert lib.swdft2d_describe(h, buf, 1024) == 0
+    assert b"kind=batched" in buf.value and b"32x32" in buf.value
+    # no adjoint for batched plans, and no FP64 algorithm
+    assert lib.swdft2d_backward(h, 0x10000, 0x90000000, None) == S["SWDFT_E_PLAN"]
+    assert lib.swdft2d_set_algo(h, _lib.SWDFT_ALGO_DIRECT_F64) == S["SWDFT_E_DTYPE"]
+    assert lib.swdft2d_set_algo(h, _lib.SWDFT_ALGO_DENSE_BF16X2) == 0
+    assert lib.swdft2d_tune(h, None, 0x10000, None) == S["SWDFT_E_ARG"]
+    # x and y overlapping
+    assert lib.swdft2d_exec(h, 0x10000, 0x10000 + 4096, None) == S["SWDFT_E_ARG"]
+    assert lib.swdft2d_destroy(h) == 0
+    assert lib.swdft2d_plan_batched(None, None, 1, 0) == S["SWDFT_E_ARG"]
+    st, _ = make_batched([])
+    assert _lib.STATUS[st] == "SWDFT_E_ARG"
+    cases = [
+        ([(64, 64, 4, 8)], _lib.SWDFT_R32, "SWDFT_E_WINDOW"),     # 4 not in {8,16,32}
+        ([(64, 64, 12, 8)], _lib.SWDFT_R32, "SWDFT_E_NOT_POW2"),
+        ([(16, 64, 32, 8)], _lib.SWDFT_R32, "SWDFT_E_WINDOW"),    # n0 > N0
+        ([(64, 64, 8, 8)], _lib.SWDFT_R64, "SWDFT_E_DTYPE"),
+        ([(64, 64, 8, 8)], 9, "SWDFT_E_ARG"),
+        ([(0, 64, 8, 8)], _lib.SWDFT_R32, "SWDFT_E_ARG"),
+    ]
+    for shapes, dt, name in cases:
+        st, h = make_batched(shapes, dt)
+        assert _lib.STATUS[st] == name, (shapes, lib.swdft2d_last_error())
+        assert h.value is None
+    # negative and overlapping offsets
+    st, _ = make_batched([(64, 64, 8, 8)], offsets=[(-1, 0)])
+    assert _lib.STATUS[st] == "SWDFT_E_ARG"
+    st, _ = make_batched([(64, 64, 8, 8), (64, 64, 8, 8)], offsets=[(0, 0), (4096, 100)])
+    assert _lib.STATUS[st] == "SWDFT_E_ARG" and b"overlap" in lib.swdft2d_last_error()
+    st, h = make_batched([(64, 64, 8, 8), (64, 64, 8, 8)], offsets=[(0, 0), (0, 57 * 57 * 64)])
+    assert st == 0  # shared input, disjoint outputs
+    lib.swdft2d_destroy(h)

@@ -1,0 +1,170 @@
+"""Batched plans (uneven images and window shapes, one graph launch of
+persistent per-shape kernels) and the autotuner, against the FP64 oracle and
+against single-image plans."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+TOL_DENSE = 5e-5
+
+
+@pytest.fixture(scope="module")
+def swd():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_1707_08213_amd as swd
+    return swd
+
+
+def rel_err(got, ref):
+    return float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300))
+
+
+SHAPES = [(40, 77, 8, 8), (77, 40, 16, 16), (96, 130, 32, 32), (41, 200, 8, 32),
+          (64, 64, 16, 8), (150, 33, 32, 8), (35, 99, 8, 16), (128, 64, 32, 16),
+          (70, 70, 16, 32), (33, 47, 8, 8), (200, 150, 16, 16)]
+
+
+def make_images(shapes, seed, cplx=False):
+    out = []
+    for i, (N0, N1, _, _) in enumerate(shapes):
+        if cplx:
+            out.append(workloads.normal_complex((N0, N1), seed + i))
+        else:
+            out.append(workloads.normal_real((N0, N1), seed + i))
+    return out
+
+
+@pytest.mark.parametrize("cplx", [False, True], ids=["real", "complex"])
+def test_batched_matches_oracle(swd, orc, cplx):
+    imgs = make_images(SHAPES, 40, cplx)
+    plan = swd.BatchedPlan(SHAPES, dtype=torch.complex64 if cplx else torch.float32)
+    print(f"[case] batched {plan.describe()}", flush=True)
+    x = plan.pack([torch.from_numpy(a) for a in imgs], device="cuda")
+    y = plan.forward(x)
+    torch.cuda.synchronize()
+    outs = [o.cpu().numpy() for o in plan.unpack(y)]
+    for im, (N0, N1, n0, n1), o in zip(imgs, SHAPES, outs):
+        ref = orc.swdft2d(im.astype(np.complex128 if cplx else np.float64), n0, n1)
+        assert rel_err(o, ref) <= TOL, (N0, N1, n0, n1)
+
+
+def test_batched_equals_single_plans_bitwise(swd):
+    """The tree classes run the same tile code as single-image plans with the
+    same lanes per stream: outputs must be bit-identical."""
+    imgs = [torch.from_numpy(a).cuda() for a in make_images(SHAPES, 90)]
+    outs = swd.swdft2d_batched(imgs, [(s[2], s[3]) for s in SHAPES])
+    for im, s, o in zip(imgs, SHAPES, outs):
+        single = swd.swdft2d(im, s[2], s[3])
+        assert torch.equal(torch.view_as_real(o), torch.view_as_real(single)), s
+
+
+def test_batched_graph_replays(swd):
+    """Replays of the graph with eager work and synchronisation in between, and
+    after rebinding to other buffers, all equal the first result."""
+    plan = swd.BatchedPlan(SHAPES)
+    xs = [plan.pack([torch.from_numpy(a) for a in make_images(SHAPES, s)], device="cuda")
+          for s in (1, 2)]
+    first = [plan.forward(x).clone() for x in xs]
+    y = torch.empty(plan.y_numel, dtype=torch.complex64, device="cuda")
+    for rep in range(4):
+        x = xs[rep % 2]
+        y.fill_(float("nan"))
+        junk = torch.randn(1 << 20, device="cuda").sum()  # unrelated eager work
+        plan.forward(x, out=y)
+        torch.cuda.synchronize()
+        assert torch.equal(torch.view_as_real(y), torch.view_as_real(first[rep % 2])), rep
+        del junk
+    # a fresh output buffer each time (rebinds the graph's arguments)
+    for rep in range(2):
+        z = plan.forward(xs[rep])
+        assert torch.equal(torch.view_as_real(z), torch.view_as_real(first[rep]))
+
+
+def test_batched_dense_classes(swd, orc):
+    shapes = SHAPES[:6]
+    imgs = make_images(shapes, 7)
+    plan = swd.BatchedPlan(shapes, algo="dense_bf16x2")
+    assert "dense" in plan.describe()
+    y = plan.forward(plan.pack([torch.from_numpy(a) for a in imgs], device="cuda"))
+    for im, s, o in zip(imgs, shapes, plan.unpack(y)):
+        ref = orc.swdft2d(im.astype(np.float64), s[2], s[3])
+        assert rel_err(o.cpu().numpy(), ref) <= TOL_DENSE, s
+
+
+def test_batched_ortho(swd, orc):
+    shapes = [(50, 60, 8, 16), (40, 40, 32, 8)]
+    imgs = make_images(shapes, 3)
+    plan = swd.BatchedPlan(shapes, norm="ortho")
+    y = plan.forward(plan.pack([torch.from_numpy(a) for a in imgs], device="cuda"))
+    for im, s, o in zip(imgs, shapes, plan.unpack(y)):
+        ref = orc.swdft2d(im.astype(np.float64), s[2], s[3], norm="ortho")
+        assert rel_err(o.cpu().numpy(), ref) <= TOL
+
+
+def test_tune_batched_then_exact(swd, orc, tmp_path, monkeypatch):
+    """Tuning picks per-shape tiles (and may pick the dense variant only if it
+    passes the 1e-5 gate); results stay within tolerance, and the tuning cache
+    gets one line per shape."""
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("SWDFT_AUTOTUNE_CACHE", str(cache))
+    shapes = [(300, 260, 8, 8), (260, 300, 16, 16), (200, 240, 32, 32), (180, 300, 8, 32)]
+    imgs = make_images(shapes, 11)
+    plan = swd.BatchedPlan(shapes)
+    x = plan.pack([torch.from_numpy(a) for a in imgs], device="cuda")
+    plan.tune(x)
+    print("tuned:", plan.describe())
+    y = plan.forward(x)
+    for im, s, o in zip(imgs, shapes, plan.unpack(y)):
+        ref = orc.swdft2d(im.astype(np.float64), s[2], s[3])
+        assert rel_err(o.cpu().numpy(), ref) <= TOL_DENSE, s
+    lines = cache.read_text().strip().splitlines()
+    assert len(lines) == 4 and all('"kind":"batched"' in ln for ln in lines)
+    # a new plan reads the cache at its first exec
+    plan2 = swd.BatchedPlan(shapes)
+    y2 = plan2.forward(x)
+    torch.cuda.synchronize()
+    assert plan2.describe() == plan.describe()
+    assert torch.equal(torch.view_as_real(y2), torch.view_as_real(y))
+
+
+def test_tune_single(swd, orc, tmp_path, monkeypatch):
+    monkeypatch.setenv("SWDFT_AUTOTUNE_CACHE", str(tmp_path / "t.jsonl"))
+    x_np = workloads.normal_real((300, 280), 5)
+    p = swd.Plan(300, 280, 32, 8)
+    x = torch.from_numpy(x_np).cuda().unsqueeze(0)
+    p.tune(x)
+    print("tuned:", p.describe())
+    y = p.forward(x)[0].cpu().numpy()
+    assert rel_err(y, orc.swdft2d(x_np.astype(np.float64), 32, 8)) <= TOL_DENSE
+    assert (tmp_path / "t.jsonl").read_text().count('"kind":"single"') == 1
+
+
+def test_uneven64_sampled(swd, orc):
+    """64 real FP32 images, sides from {128,256,512,1024}, windows from
+    {8x8, 16x16, 32x32, 8x32}: one batched exec, 64 sampled windows per image
+    (corners and edges included) against the oracle."""
+    imgs = workloads.uneven64()
+    shapes = [(im["x"].shape[0], im["x"].shape[1], im["n0"], im["n1"]) for im in imgs]
+    plan = swd.BatchedPlan(shapes)
+    print(f"[case] uneven64 {plan.describe()}", flush=True)
+    x = plan.pack([torch.from_numpy(im["x"]) for im in imgs], device="cuda")
+    y = plan.forward(x)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i, (im, s, o) in enumerate(zip(imgs, shapes, plan.unpack(y))):
+        P0, P1 = s[0] - s[2] + 1, s[1] - s[3] + 1
+        q0, q1 = workloads.window_sample(P0, P1, 64, 4000 + i)
+        got = o[torch.from_numpy(q0).cuda(), torch.from_numpy(q1).cuda()].cpu().numpy()
+        ref = orc.swdft2d(im["x"].astype(np.float64), s[2], s[3], windows=(q0, q1))
+        e = rel_err(got, ref)
+        worst = max(worst, e)
+        assert e <= TOL, (i, s)
+    print(f"uneven64: worst per-image normwise error {worst:.2e}")
+    del y
+    torch.cuda.empty_cache()
