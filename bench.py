@@ -16,6 +16,8 @@ Other workloads (one JSON line each, same fields where they apply):
   cplx2048 - 2048 x 512 complex64, 32 x 8 windows (tree; dense MFMA variant).
   grad256  - 16 x 256 x 256 real FP32, 16 x 16 windows, forward + adjoint of
              L = sum w |A|^2 (band mask w); the adjoint kernel is read-bound.
+  uneven64 - 64 real FP32 images of uneven sizes and window shapes in one
+             batched graph launch, after autotuning.
 """
 from __future__ import annotations
 
@@ -369,7 +371,66 @@ def run_grad256(args, swd, dev) -> dict:
     return out
 
 
-WORKLOADS = {"sin1024": run_sin1024, "cplx2048": run_cplx2048, "grad256": run_grad256}
+def run_uneven64(args, swd, dev) -> dict:
+    import numpy as np
+    import torch
+
+    import workloads
+    imgs = workloads.uneven64()
+    shapes = [(im["x"].shape[0], im["x"].shape[1], im["n0"], im["n1"]) for im in imgs]
+    plan = swd.BatchedPlan(shapes)
+    x = plan.pack([torch.from_numpy(im["x"]) for im in imgs], device=dev)
+    y = torch.empty(plan.y_numel, dtype=torch.complex64, device=dev)
+    coeffs = plan.output_elems()
+    alg_bytes = coeffs * 8 + x.numel() * 4
+    stream = torch.cuda.current_stream(dev)
+    log(f"untuned: {plan.describe()}")
+    for _ in range(max(1, args.warmup // 2)):
+        plan.forward(x, out=y)
+    torch.cuda.synchronize()
+    u_ms, u_wall, _ = time_launches(lambda: plan.forward(x, out=y), max(3, args.steps // 5), stream)
+    t0 = time.perf_counter()
+    plan.tune(x, out=y)
+    tune_s = time.perf_counter() - t0
+    log(f"tuned in {tune_s:.1f} s: {plan.describe()}")
+    for _ in range(max(1, args.warmup // 2)):
+        plan.forward(x, out=y)
+    torch.cuda.synchronize()
+    steps = max(3, args.steps // 5)
+    avg_ms, wall, _ = time_launches(lambda: plan.forward(x, out=y), steps, stream)
+    step_s = wall / steps
+    rf = roofline(alg_bytes, avg_ms, "persistent per-shape kernels (one graph launch)")
+    log(f"batched: {avg_ms:.2f} ms/launch ({rf['achieved']:.0f} GB/s), untuned {u_ms:.2f} ms")
+    err, cpu = None, None
+    if not args.no_cpu_baseline:
+        import oracle
+        orc = oracle.get()
+        errs, t_or, n_or = [], 0.0, 0
+        outs = plan.unpack(y)
+        for i, (im, s) in enumerate(zip(imgs, shapes)):
+            P0, P1 = s[0] - s[2] + 1, s[1] - s[3] + 1
+            q0, q1 = workloads.window_sample(P0, P1, 32, 5000 + i)
+            got = sampled(outs[i], q0, q1)
+            t1 = time.perf_counter()
+            ref = orc.swdft2d(im["x"].astype(np.float64), s[2], s[3], windows=(q0, q1))
+            t_or += time.perf_counter() - t1
+            n_or += q0.size * s[2] * s[3]
+            errs.append(rel(got, ref))
+        err = max(errs)
+        cpu = {"value": n_or / t_or, "unit": "coeffs/s", "cores": orc.num_threads(),
+               "kind": "oracle", "sample": f"32 windows per image, {n_or} coefficients"}
+    del y
+    out = base_record(args, coeffs / step_s, step_s * 1e3, "f32", {
+        "workload": "uneven64: 64 real FP32 images, sides from {128,256,512,1024}, windows from "
+                    "{8x8,16x16,32x32,8x32}, one graph launch of persistent per-shape kernels",
+        "images": len(shapes), "batch": len(shapes), "algo": "batched", "coeffs_per_step": coeffs})
+    out.update({"roofline": rf, "rel_err": err, "untuned_ms": u_ms, "tune_seconds": tune_s,
+                "plan": plan.describe(), "cpu_baseline": cpu})
+    return out
+
+
+WORKLOADS = {"sin1024": run_sin1024, "cplx2048": run_cplx2048, "grad256": run_grad256,
+             "uneven64": run_uneven64}
 
 
 def main() -> int:

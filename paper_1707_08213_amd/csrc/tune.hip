@@ -101,6 +101,20 @@ swdft_status_t copy_prefix(const void* y, size_t elems, std::vector<float2>* out
 
 constexpr double kGate = 1e-5;
 constexpr size_t kGateBytes = 8u << 20;
+// The dense variant (error ~5e-6) must beat the tree (error ~2e-7) by this
+// factor to be chosen; near-ties keep the more accurate tree.
+constexpr float kDenseMargin = 0.97f;
+
+int pick(const std::vector<Candidate>& cands, int best_tree, bool dense_ok) {
+  int best = best_tree;
+  for (int i = 0; i < (int)cands.size(); ++i) {
+    if (!cands[i].dense || !dense_ok) continue;
+    const float bar = best_tree >= 0 ? cands[best_tree].us * kDenseMargin : 3.4e38f;
+    if (cands[i].us < bar && (best < 0 || cands[best].dense == false || cands[i].us < cands[best].us))
+      best = i;
+  }
+  return best;
+}
 
 void append_cache(const std::string& line) {
   const char* path = std::getenv("SWDFT_AUTOTUNE_CACHE");
@@ -199,11 +213,7 @@ swdft_status_t tune_single(swdft2d_plan_s* p, const void* x, void* y, hipStream_
     }
     dense_ok = normwise_diff(got, ref) <= kGate;
   }
-  int best = -1;
-  for (int i = 0; i < (int)cands.size(); ++i) {
-    if (cands[i].dense && !dense_ok) continue;
-    if (best < 0 || cands[i].us < cands[best].us) best = i;
-  }
+  const int best = pick(cands, best_tree, dense_ok);
   if (best < 0) {
     *p = saved;
     return fail(SWDFT_E_DTYPE, "no candidate passed the accuracy gate");
@@ -280,11 +290,7 @@ swdft_status_t tune_batched(swdft2d_plan_s* p, const void* x, void* y, hipStream
       if (st != SWDFT_OK) return st;
       dense_ok = normwise_diff(got, ref) <= kGate;
     }
-    int best = -1;
-    for (int i = 0; i < (int)cands.size(); ++i) {
-      if (cands[i].dense && !dense_ok) continue;
-      if (best < 0 || cands[i].us < cands[best].us) best = i;
-    }
+    const int best = pick(cands, best_tree, dense_ok);
     if (best < 0) return fail(SWDFT_E_DTYPE, "no candidate passed the accuracy gate");
     bs->cfg[key] = ClassCfg{cands[best].dense, cands[best].slab};
     bs->tables_dirty = true;
