@@ -91,6 +91,9 @@ typedef int swdft_status_t;
 #define SWDFT_E_PLAN 9        /* null or destroyed plan, or wrong plan kind */
 
 #define SWDFT_MAX_WINDOW 32   /* largest n0 or n1 a plan accepts */
+#define SWDFT_MAX_ROW 4194304 /* largest N1 a plan accepts: 64 input rows of it
+                                 (the most one tile stages) stay below 2 GiB,
+                                 so kernels address them with 32-bit offsets */
 
 typedef struct swdft2d_plan_s* swdft2d_plan_t;
 
@@ -98,8 +101,8 @@ typedef struct swdft2d_plan_s* swdft2d_plan_t;
  * Checks, in this order: out != NULL (E_ARG); N0, N1, n0, n1, batch >= 1 and
  * dtype known (E_ARG); n0, n1 powers of two (E_NOT_POW2); n_i <= N_i and
  * n_i <= SWDFT_MAX_WINDOW (E_WINDOW); batch*P0*P1*n0*n1 and its byte count fit
- * in int64 (E_OVERFLOW). Builds the twiddle vectors Omega^0, Omega^1 of
- * Sec. 4.2 in FP64 (exact at quarter turns, Omega[m + n/2] = -Omega[m]) and
+ * in int64, and N1 <= SWDFT_MAX_ROW (E_OVERFLOW). Builds the twiddle vectors
+ * Omega^0, Omega^1 of Sec. 4.2 in FP64 (exact at quarter turns, Omega[m + n/2] = -Omega[m]) and
  * rounds them once to FP32. Touches no GPU. On error *out is set to NULL. */
 swdft_status_t swdft2d_plan(swdft2d_plan_t* out, int64_t N0, int64_t N1, int32_t n0, int32_t n1,
                             swdft_dtype_t dtype, int64_t batch);
@@ -168,7 +171,8 @@ typedef struct {
  * one exec. dtype must be R32 or C32 (E_DTYPE otherwise). Checks each
  * descriptor as swdft2d_plan does (E_ARG, E_NOT_POW2, E_WINDOW), rejects
  * window sizes outside {8,16,32} (E_WINDOW), negative offsets and overlapping
- * output ranges (E_ARG), and sizes that overflow int64 (E_OVERFLOW). Images
+ * output ranges (E_ARG), and sizes that overflow int64 or N1 above
+ * SWDFT_MAX_ROW (E_OVERFLOW). Images
  * are grouped by window shape; each group runs its own persistent kernel (a
  * grid of the waves the chip keeps resident pulling tiles from a work list
  * sorted by decreasing output bytes). At the first exec the plan uploads its
@@ -180,7 +184,8 @@ swdft_status_t swdft2d_plan_batched(swdft2d_plan_t* out, const swdft2d_desc_t* d
                                     swdft_dtype_t dtype);
 
 /* Time candidate configurations on the caller's x and y and keep the fastest:
- * tree tile shapes (lanes per column stream, slab length) and, when the
+ * tree tile shapes (lanes per column stream, slab length, resident waves per
+ * CU) and, when the
  * plan's algorithm is AUTO (or DENSE_BF16X2) and the window shape allows, the
  * dense matrix-core variant, which is admitted only if its output agrees with
  * the tree's to a normwise relative difference of 1e-5. Batched plans are

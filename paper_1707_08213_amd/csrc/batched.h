@@ -46,7 +46,7 @@ struct BatchArgs {
 // Persistent class kernels exist for n0, n1 in {8, 16, 32}.
 bool batched_shape_supported(int n0, int n1);
 // lanes per column stream of the tree path the batched kernels compile
-int batched_tree_kg(int n0);
+int batched_tree_kg(int n0, int n1);
 // kernel symbol of a class (nullptr if none)
 const void* batched_tree_symbol(int n0, int n1, bool real_input);
 const void* batched_dense_symbol(int n0, int n1, bool real_input);

@@ -151,7 +151,7 @@ swdft_status_t upload(T** dst, size_t* cap, const std::vector<T>& src, const cha
 
 int batched_default_slab(int n0, int n1, bool dense) {
   if (dense) return 64;
-  const int kg = batched_tree_kg(n0);
+  const int kg = batched_tree_kg(n0, n1);
   const int cr = tree_fwd_rows_per_chunk(n0, n1, kg);
   int S = std::max(64, 4 * (n0 - 1));
   return (int)(ceil_div(S, cr) * cr);
@@ -176,7 +176,7 @@ void batched_build_tables(swdft2d_plan_s* p) {
     make_twiddles_f32(n0, run.tw.w0);
     make_twiddles_f32(n1, run.tw.w1);
     run.item_begin = (int64_t)bs->items.size();
-    const int kg = batched_tree_kg(n0);
+    const int kg = batched_tree_kg(n0, n1);
     const int cr = tree_fwd_rows_per_chunk(n0, n1, kg);
     int slab = cfg.slab > 0 ? cfg.slab : batched_default_slab(n0, n1, cfg.dense);
     std::vector<std::pair<int64_t, BatchItem>> costed;
@@ -362,7 +362,7 @@ extern "C" swdft_status_t swdft2d_plan_batched(swdft2d_plan_t* out, const swdft2
       return fail(SWDFT_E_ARG, "image %lld: negative offset", (long long)i);
     const int64_t P0 = d.N0 - d.n0 + 1, P1 = d.N1 - d.n1 + 1;
     int64_t o = 0, xe = 0;
-    if (P0 > INT32_MAX || P1 > INT32_MAX || !mul_ok(P0, P1, &o) ||
+    if (d.N1 > SWDFT_MAX_ROW || P0 > INT32_MAX || P1 > INT32_MAX || !mul_ok(P0, P1, &o) ||
         !mul_ok(o, (int64_t)d.n0 * d.n1, &o) || !mul_ok(d.N0, d.N1, &xe) ||
         d.x_offset > INT64_MAX / 16 - xe || d.y_offset > INT64_MAX / 16 - o ||
         out_elems > INT64_MAX / 16 - o)

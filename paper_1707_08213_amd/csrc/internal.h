@@ -35,6 +35,10 @@ struct TreeGeom {
   int32_t batch;
   int32_t kg;              // lanes per column stream (k0 residues), 1 or 2
   float scale;             // 1 or 1/sqrt(n0 n1)
+  int32_t wpc;             // resident waves per CU: 0 = as many as fit, else capped
+  int32_t lds_cu;          // LDS bytes per CU (used to impose the cap)
+  int32_t order;           // tile order: 0 = a contiguous range per XCD, 1 = dispatch order
+  int32_t pad_;
 };
 
 // Geometry of one adjoint launch. One wave owns a strip of window columns and
@@ -82,6 +86,7 @@ int tree_fwd_rows_per_chunk(int n0, int n1, int kg);
 // lanes per column stream used when the caller does not choose
 int tree_fwd_default_kg(int n0, int n1);
 bool tree_fwd_kg_supported(int n0, int n1, int kg);
+int tree_fwd_resident_waves(int wpc, int ncu);
 
 hipError_t launch_tree_adj(int n0, int n1, bool real_input, const float2* dy, void* ws, void* dx,
                            const AdjGeom& g, const TwiddlesF32& tw, hipStream_t stream);

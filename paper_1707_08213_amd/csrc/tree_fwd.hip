@@ -16,8 +16,15 @@ int tree_fwd_rows_per_chunk(int n0, int n1, int kg) {
 }
 
 // A stream is split over two lanes when its register rings would otherwise
-// limit the kernel to one wave per SIMD (n0 = 32).
-int tree_fwd_default_kg(int n0, int n1) { return (n0 == 32 && n1 <= 32) ? 2 : 1; }
+// limit the kernel to one wave per SIMD (n0 = 32); for n0 = 8, whose short
+// output rows per wave need more waves in flight; and for n1 = 8, where the
+// two lanes of a stream write adjacent 64-byte k0 rows, so each store
+// instruction covers whole 128-byte lines.
+int tree_fwd_default_kg(int n0, int n1) {
+  return (n0 >= 8 && n1 <= 32 && (n0 == 32 || n0 == 8 || n1 == 8)) ? 2 : 1;
+}
+
+int tree_fwd_resident_waves(int wpc, int ncu) { return wpc > 0 && ncu > 0 ? wpc * ncu : 0; }
 
 bool tree_fwd_kg_supported(int n0, int n1, int kg) {
   return kg == 1 || (kg == 2 && n0 >= 8 && n1 <= 32);

@@ -28,10 +28,23 @@
 //    consecutive windows, i.e. whole 128-byte lines, with non-temporal
 //    stores; the output is the only large HBM stream.
 //  * The first n0-1 rows of a slab only prime the rings (their windows belong
-//    to the previous slab); their outputs are not stored. Partial trees near
+//    to the previous slab); their outputs are not stored. Stores go through a
+//    buffer resource per output row whose range ends at the strip's last
+//    window (empty for priming rows): the hardware drops out-of-range lanes,
+//    so the store stream has no exec-mask branches. Partial trees near
 //    the top and left edges (Sec. 4.7) read zeros and are never stored.
-//  * Workgroup ids are remapped so that each XCD (own L2) gets a contiguous
-//    range of tiles: neighbouring strips share input columns.
+//  * Occupancy and tile order: the host may cap the resident waves per CU
+//    (extra dynamic LDS that the kernel does not touch). With one wave per
+//    CU and a wave per whole column of its strip, the resident waves write
+//    one band of consecutive output rows that moves down the image; tiles
+//    then run in dispatch order so that each round of resident waves covers
+//    one contiguous range of strips. Without a cap, workgroup ids are
+//    remapped so that each XCD (own L2) gets a contiguous range of tiles:
+//    neighbouring strips share input columns.
+//  * Inputs of the next chunk are loaded (through a buffer resource that
+//    returns zero past the image) before the column phase of the current
+//    chunk, whose stores then separate the loads from their use: the wait
+//    for the inputs never drains the output stores.
 #pragma once
 #include <type_traits>
 
@@ -55,14 +68,14 @@ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 
-// Load a value that is the same for every lane of the wave and keep it in
-// scalar registers. Used for twiddles and tile geometry, which the persistent
-// batched kernel reads from a device table at addresses the compiler cannot
-// prove unmodified (so it would otherwise hold them in vector registers).
+// Load a value that is the same for every lane of the wave, through the
+// constant address space so that it is fetched by a scalar load into scalar
+// registers. Used for twiddles, which live in the kernel arguments or in a
+// device table that no kernel writes.
 __device__ __forceinline__ float2 uload(const float2* p) {
-  const float2 v = *p;
-  return make_float2(__builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v.x))),
-                     __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v.y))));
+  typedef const __attribute__((address_space(4))) float* const_ptr;
+  const const_ptr q = (const_ptr)(reinterpret_cast<const float*>(p));
+  return make_float2(q[0], q[1]);
 }
 
 template <typename T>
@@ -201,6 +214,43 @@ __device__ __forceinline__ void store_nt(float2* p, float2 v) {
   __builtin_nontemporal_store(t, reinterpret_cast<f2v*>(p));
 }
 
+// Buffer resource over [base, base + nbytes): a raw buffer store whose byte
+// offset is at or past nbytes is dropped by the hardware. The tree stores its
+// output through one such resource per output row and strip, so that lanes
+// past the right edge and rows outside the slab need no branch.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t nbytes) {
+  constexpr int kRawBufferFormat = 0x00020000;  // word 3 of a raw (untyped) gfx9 buffer
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)nbytes,
+                                           kRawBufferFormat);
+}
+
+typedef unsigned u2v __attribute__((ext_vector_type(2)));
+
+// A byte offset no buffer of this library reaches (ranges stay below 2 GiB):
+// a load there returns zero, a store there is dropped.
+constexpr uint32_t kOutOfRange = 0x80000000u;
+
+// Input element at byte offset off of a buffer resource; zero past its end.
+template <bool REAL>
+__device__ __forceinline__ std::conditional_t<REAL, float, float2> load_buf(
+    __amdgpu_buffer_rsrc_t r, uint32_t off) {
+  if constexpr (REAL) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+  } else {
+    const u2v t = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+    return make_float2(__uint_as_float(t.x), __uint_as_float(t.y));
+  }
+}
+
+// Non-temporal 8-byte store at byte offset off of a buffer resource.
+__device__ __forceinline__ void store_buf_nt(__amdgpu_buffer_rsrc_t r, uint32_t off, float2 v) {
+  constexpr int kNonTemporal = 2;
+  u2v t;
+  t.x = __float_as_uint(v.x);
+  t.y = __float_as_uint(v.y);
+  __builtin_amdgcn_raw_buffer_store_b64(t, r, (int)off, 0, kNonTemporal);
+}
+
 // Workgroup i runs on XCD i mod 8; give each XCD a contiguous block of tiles.
 __device__ __forceinline__ int xcd_tile(int id, int nb) {
   constexpr int kXcd = 8;
@@ -243,22 +293,54 @@ __device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float
   const int nrows = (int)(q0_end - row0) + N0W - 1;
   const int nchunks = (nrows + C::CR - 1) / C::CR;
 
-  const float* xr = reinterpret_cast<const float*>(xv) + (REAL ? b * g.x_image_stride : 0);
-  const float2* xc = reinterpret_cast<const float2*>(xv) + (REAL ? 0 : b * g.x_image_stride);
+  using XT = std::conditional_t<REAL, float, float2>;
+  constexpr int EB = (int)sizeof(XT);
+  const XT* ximg = reinterpret_cast<const XT*>(xv) + b * g.x_image_stride;
   float2* yimg = y + b * g.y_image_stride;
 
   // row-phase roles: lane (r, c) = input row r of the pass, window column c
   const int rp_r = lane / C::QW;
   const int rp_c = lane % C::QW;
   const int64_t rp_q1 = q1_0 + rp_c;
+  // byte offset of the lane's input x[r][q1 + n1 - 1 - d] within a chunk of
+  // rows; columns past the image edge read zero (Sec. 4.7)
+  uint32_t x_off[N1W];
+  sfor<0, N1W>([&](auto D) {
+    constexpr int d = D;
+    const int64_t col = rp_q1 + (N1W - 1 - d);
+    x_off[d] = col < g.N1 ? (uint32_t)(((int64_t)rp_r * g.N1 + col) * EB) : kOutOfRange;
+  });
+  // Raw inputs of one chunk (CR rows from crow), loaded a chunk ahead so that
+  // their latency hides behind the column phase of the previous chunk. Rows
+  // past the image bottom lie outside the resource and read zero.
+  constexpr int PASSES = C::CR / C::R;
+  XT xin[PASSES][N1W];
+  auto load_chunk = [&](int64_t crow) {
+    const int64_t rows = min((int64_t)C::CR, g.N0 - crow);
+    const auto rs = buf_rsrc(ximg + (rows > 0 ? crow : 0) * g.N1,
+                             rows > 0 ? (uint32_t)(rows * g.N1 * EB) : 0u);
+    sfor<0, PASSES>([&](auto PS) {
+      constexpr int ps = PS;
+      sfor<0, N1W>([&](auto D) {
+        constexpr int d = D;
+        xin[ps][d] = load_buf<REAL>(rs, x_off[d] + (uint32_t)(ps * C::R * g.N1 * EB));
+      });
+    });
+  };
+
   // column-phase roles: lane (c, res, k1)
   const int cp_c = lane / (N1W * KG);
   const int cp_res = (lane / N1W) % KG;
   const int cp_k1 = lane % N1W;
-  const int64_t cp_q1 = q1_0 + cp_c;
-  const bool cp_ok = cp_q1 < g.P1;
-  float2* ycol = yimg + cp_q1 * (N0W * N1W) + cp_res * N1W + cp_k1;
+  // Output of one row of the strip: QW windows of n0*n1 values from ystrip +
+  // q0 * y_row_stride; only the first strip_bytes exist (the last strip of a
+  // row may be partial).
+  float2* ystrip = yimg + q1_0 * (N0W * N1W);
   const int64_t y_row_stride = g.P1 * (N0W * N1W);
+  const uint32_t strip_bytes =
+      (uint32_t)(min((int64_t)C::QW, g.P1 - q1_0) * (N0W * N1W * (int)sizeof(float2)));
+  const uint32_t lane_off =
+      (uint32_t)((cp_c * (N0W * N1W) + cp_res * N1W + cp_k1) * (int)sizeof(float2));
 
   float2 lanefac[CC::M0 + 1];
   lanefac[0] = make_float2(1.f, 0.f);
@@ -275,23 +357,18 @@ __device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float
   float2 ring[CC::RING_TOTAL];
   sfor<0, CC::RING_TOTAL>([&](auto K) { ring[K] = make_float2(0.f, 0.f); });
 
-  for (int c = 0; c < nchunks; ++c) {
-    const int64_t crow = row0 + (int64_t)c * C::CR;
-
-    // ---- row phase: CR rows x QW window columns of Z into LDS
-    sfor<0, C::CR / C::R>([&](auto PS) {
+  // ---- row phase: the CR rows x QW window columns of Z of one chunk, from
+  // the raw inputs in xin, into LDS
+  auto row_phase = [&]() {
+    sfor<0, PASSES>([&](auto PS) {
       constexpr int ps = PS;
-      const int64_t row = crow + ps * C::R + rp_r;
-      const bool row_ok = row < g.N0;
       float2 v[N1W];
       sfor<0, N1W>([&](auto D) {
         constexpr int d = D;
-        const int64_t col = rp_q1 + (N1W - 1 - d);
-        const bool ok = row_ok && col < g.N1;
         if constexpr (REAL) {
-          v[d] = make_float2(ok ? xr[row * g.N1 + col] : 0.f, 0.f);
+          v[d] = make_float2(xin[ps][d], 0.f);
         } else {
-          v[d] = ok ? xc[row * g.N1 + col] : make_float2(0.f, 0.f);
+          v[d] = xin[ps][d];
         }
       });
       row_levels<N1W>(v, w1);
@@ -301,24 +378,50 @@ __device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float
       float2* zrow = zl + (ps * C::R + rp_r) * C::ZROW + rp_c * C::ZS;
       sfor<0, N1W>([&](auto K) { zrow[K] = v[K]; });
     });
-    __syncthreads();
+  };
 
-    // ---- column phase: CR steps down the slab, one input row each
+  // The loop is rotated: iteration c issues the loads of chunk c+1, runs the
+  // column phase of chunk c (whose stores then sit between those loads and
+  // their use) and only then the row phase of chunk c+1, so the wait for the
+  // inputs never has to drain the output stores.
+  load_chunk(row0);
+  row_phase();
+  __syncthreads();
+  for (int c = 0; c < nchunks; ++c) {
+    const int64_t crow = row0 + (int64_t)c * C::CR;
+    // past the last chunk this reads zeros and touches no memory
+    load_chunk(crow + C::CR);
+    __builtin_amdgcn_sched_barrier(0);
+
+    // ---- column phase: CR steps down the slab, one input row each. The Z
+    // value of a step is read from LDS kLdsAhead steps before it is used.
+    constexpr int kLdsAhead = 2;
+    const float2* zcol = zl + cp_c * C::ZS + cp_k1;
+    float2 zq[C::CR];
+    sfor<0, (kLdsAhead < C::CR ? kLdsAhead : C::CR)>([&](auto K) { zq[K] = zcol[K * C::ZROW]; });
     sfor<0, C::CR>([&](auto STc) {
       constexpr int st = STc;
-      const float2 z = zl[st * C::ZROW + cp_c * C::ZS + cp_k1];
+      if constexpr (st + kLdsAhead < C::CR) zq[st + kLdsAhead] = zcol[(st + kLdsAhead) * C::ZROW];
+      __builtin_amdgcn_sched_barrier(0);  // keep the read ahead of this step's work
+      const float2 z = zq[st];
       const int64_t q0 = crow + st - (N0W - 1);
-      const bool store = (q0 >= row0) && (q0 < q0_end) && cp_ok;
-      float2* dst = ycol + q0 * y_row_stride;
+      // priming rows (and rows past the slab) get an empty resource
+      const bool row_store = (q0 >= row0) && (q0 < q0_end);
+      const auto out = buf_rsrc(ystrip + (row_store ? q0 : 0) * y_row_stride,
+                                row_store ? strip_bytes : 0u);
       if constexpr (N0W == 1) {
-        if (store) store_nt(dst, z);
+        store_buf_nt(out, lane_off, z);
       } else {
         column_levels<N0W, KG, st % C::RING>(z, ring, lanefac, w0, [&](auto J, float2 v) {
-          if (store) store_nt(dst + (KG * J) * N1W, v);
+          store_buf_nt(out, lane_off + (KG * J) * N1W * (int)sizeof(float2), v);
         });
       }
     });
     __syncthreads();
+    if (c + 1 < nchunks) {
+      row_phase();
+      __syncthreads();
+    }
   }
 }
 
@@ -328,12 +431,21 @@ __global__ __launch_bounds__(64) void tree_fwd_kernel(const void* __restrict__ x
                                                       TwiddlesF32 tw) {
   using C = TreeCfg<N0W, N1W, REAL, KG>;
   __shared__ float2 zl[C::LDS_FLOAT2];
-  int id = xcd_tile(blockIdx.x, gridDim.x);
+  int id = g.order ? (int)blockIdx.x : xcd_tile(blockIdx.x, gridDim.x);
   const int strip = id % g.nstrips;
   id /= g.nstrips;
   const int slab = id % g.nslabs;
   const int b = id / g.nslabs;
   tree_fwd_tile<N0W, N1W, REAL, KG>(xv, y, g, tw.w0, tw.w1, strip, slab, b, zl);
+}
+
+// Dynamic LDS that caps the resident waves per CU at wpc (one wave per
+// workgroup): the workgroup's total LDS is set midway between lds_cu/(wpc+1)
+// and lds_cu/wpc. The kernel does not touch it.
+inline unsigned occupancy_lds(int wpc, int lds_cu, unsigned static_lds) {
+  if (wpc <= 0 || lds_cu <= 0) return 0u;
+  const unsigned want = (unsigned)(lds_cu / wpc + lds_cu / (wpc + 1)) / 2u;
+  return want > static_lds ? want - static_lds : 0u;
 }
 
 template <int N0W, int N1W, bool REAL>
@@ -342,13 +454,17 @@ hipError_t launch_one(const void* x, float2* y, const TreeGeom& g, const Twiddle
   const int64_t nb = (int64_t)g.batch * g.nslabs * g.nstrips;
   if constexpr (N0W >= 8 && N1W <= 32) {
     if (g.kg == 2) {
-      hipLaunchKernelGGL((tree_fwd_kernel<N0W, N1W, REAL, 2>), dim3((unsigned)nb), dim3(64), 0,
+      const unsigned pad = occupancy_lds(
+          g.wpc, g.lds_cu, TreeCfg<N0W, N1W, REAL, 2>::LDS_FLOAT2 * (unsigned)sizeof(float2));
+      hipLaunchKernelGGL((tree_fwd_kernel<N0W, N1W, REAL, 2>), dim3((unsigned)nb), dim3(64), pad,
                          stream, x, y, g, tw);
       return hipGetLastError();
     }
   }
   if (g.kg != 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((tree_fwd_kernel<N0W, N1W, REAL, 1>), dim3((unsigned)nb), dim3(64), 0, stream,
+  const unsigned pad = occupancy_lds(
+      g.wpc, g.lds_cu, TreeCfg<N0W, N1W, REAL, 1>::LDS_FLOAT2 * (unsigned)sizeof(float2));
+  hipLaunchKernelGGL((tree_fwd_kernel<N0W, N1W, REAL, 1>), dim3((unsigned)nb), dim3(64), pad, stream,
                      x, y, g, tw);
   return hipGetLastError();
 }

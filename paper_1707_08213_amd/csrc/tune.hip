@@ -2,8 +2,9 @@
 // accuracy gate, and a cache of the results.
 //
 // swdft2d_tune times candidate configurations on the caller's buffers and
-// keeps the fastest. Candidates: the tree with 1 or 2 lanes per column stream
-// and three slab lengths, and (where the shape allows and the plan's
+// keeps the fastest. Candidates: the tree with 1 or 2 lanes per column stream,
+// slab lengths from a whole column down to about 4096 tiles, and resident
+// waves per CU uncapped, 1 or 2; and (where the shape allows and the plan's
 // algorithm is AUTO or DENSE) the dense matrix-core variant with two slab
 // lengths. The dense variant is admitted only if its output agrees with the
 // tree's to a normwise relative difference of 1e-5 on the first
@@ -13,7 +14,7 @@
 // Cache: when SWDFT_AUTOTUNE_CACHE names a file, results are appended to it as
 // one JSON object per line, and plans consult it at their first exec:
 //   {"arch":"gfx950","kind":"single","n0":16,"n1":16,"real":1,"size":20,
-//    "algo":"tree","kg":1,"slab":64,"us":317.1}
+//    "algo":"tree","kg":1,"slab":1024,"wpc":1,"us":317.1}
 // ("size" is floor(log2(windows per launch)); batched entries have
 // "kind":"batched" and no size). The last matching line wins.
 #include <algorithm>
@@ -36,6 +37,7 @@ struct Candidate {
   int kg = 1;
   int slab = 0;
   float us = 0.f;
+  int wpc = -1;  // tree: resident waves per CU (0 = no cap); -1 = automatic
 };
 
 std::string device_arch() {
@@ -150,17 +152,29 @@ swdft_status_t tune_single(swdft2d_plan_s* p, const void* x, void* y, hipStream_
   const swdft2d_plan_s saved = *p;
   std::vector<Candidate> cands;
   if (allow_tree) {
+    // slabs: the automatic choice for each cap, the whole column, and about
+    // 256 to 4096 tiles; caps: none, one or two resident waves per CU
     for (int kg : {1, 2}) {
       if (!tree_fwd_kg_supported(p->n0, p->n1, kg)) continue;
-      p->tree_kg = kg;
-      p->tree_slab = 0;
-      const int S = tree_geom(p).S;
       const int cr = tree_fwd_rows_per_chunk(p->n0, p->n1, kg);
-      for (int s : {S / 2, S, 2 * S}) {
-        const int sl = (int)(ceil_div(std::max(s, cr), cr) * cr);
-        bool dup = false;
-        for (auto& c : cands) dup |= (!c.dense && c.kg == kg && c.slab == sl);
-        if (!dup) cands.push_back({false, kg, sl, 0.f});
+      const int64_t columns =
+          ceil_div(p->P1, tree_fwd_columns_per_wave(p->n0, p->n1, kg)) * p->batch;
+      std::vector<int64_t> slabs = {p->P0};
+      for (int64_t tiles : {256, 512, 1024, 4096}) slabs.push_back(ceil_div(p->P0 * columns, tiles));
+      for (int wpc : {0, 1, 2}) {
+        p->tree_kg = kg;
+        p->tree_wpc = wpc;
+        p->tree_slab = 0;
+        slabs.push_back(tree_geom(p).S);
+      }
+      for (int64_t s : slabs) {
+        int64_t sl = ceil_div(std::max<int64_t>(s, cr), cr) * cr;
+        sl = std::min<int64_t>(sl, ceil_div(p->P0, cr) * cr);
+        for (int wpc : {0, 1, 2}) {
+          bool dup = false;
+          for (auto& c : cands) dup |= (!c.dense && c.kg == kg && c.slab == sl && c.wpc == wpc);
+          if (!dup) cands.push_back({false, kg, (int)sl, 0.f, wpc});
+        }
       }
     }
   }
@@ -176,6 +190,7 @@ swdft_status_t tune_single(swdft2d_plan_s* p, const void* x, void* y, hipStream_
       p->tuned_algo = SWDFT_ALGO_TREE;
       p->tree_kg = c.kg;
       p->tree_slab = c.slab;
+      p->tree_wpc = c.wpc;
     }
   };
   auto run = [&]() -> swdft_status_t {
@@ -222,10 +237,10 @@ swdft_status_t tune_single(swdft2d_plan_s* p, const void* x, void* y, hipStream_
   char line[512];
   std::snprintf(line, sizeof(line),
                 "{\"arch\":\"%s\",\"kind\":\"single\",\"n0\":%d,\"n1\":%d,\"real\":%d,\"size\":%d,"
-                "\"algo\":\"%s\",\"kg\":%d,\"slab\":%d,\"us\":%.1f}",
+                "\"algo\":\"%s\",\"kg\":%d,\"slab\":%d,\"wpc\":%d,\"us\":%.1f}",
                 device_arch().c_str(), p->n0, p->n1, real ? 1 : 0,
                 size_class(p->P0 * p->P1 * p->batch), cands[best].dense ? "dense" : "tree",
-                cands[best].kg, cands[best].slab, cands[best].us);
+                cands[best].kg, cands[best].slab, cands[best].wpc, cands[best].us);
   append_cache(line);
   return SWDFT_OK;
 }
@@ -246,7 +261,7 @@ swdft_status_t tune_batched(swdft2d_plan_s* p, const void* x, void* y, hipStream
     std::vector<Candidate> cands;
     if (allow_tree) {
       const int d = batched_default_slab(n0, n1, false);
-      for (int s : {d / 2, d, 2 * d}) cands.push_back({false, batched_tree_kg(n0), s, 0.f});
+      for (int s : {d / 2, d, 2 * d}) cands.push_back({false, batched_tree_kg(n0, n1), s, 0.f});
     }
     if (allow_dense)
       for (int s : {64, 128}) cands.push_back({true, 1, s, 0.f});
@@ -322,13 +337,14 @@ void apply_cached_tuning(swdft2d_plan_s* p) {
   while (std::fgets(buf, sizeof(buf), f)) {
     const std::string s(buf);
     std::string a, kind, algo;
-    long long n0 = 0, n1 = 0, r = 0, size = -1, kg = 1, slab = 0;
+    long long n0 = 0, n1 = 0, r = 0, size = -1, kg = 1, slab = 0, wpc = -1;
     if (!json_str(s, "arch", &a) || a != arch || !json_str(s, "kind", &kind) ||
         !json_str(s, "algo", &algo) || !json_int(s, "n0", &n0) || !json_int(s, "n1", &n1) ||
         !json_int(s, "real", &r) || (r != 0) != real)
       continue;
     json_int(s, "kg", &kg);
     json_int(s, "slab", &slab);
+    json_int(s, "wpc", &wpc);
     const bool dense = algo == "dense";
     if (p->kind == 0 && kind == "single" && n0 == p->n0 && n1 == p->n1 &&
         json_int(s, "size", &size) && size == size_class(p->P0 * p->P1 * p->batch)) {
@@ -339,6 +355,7 @@ void apply_cached_tuning(swdft2d_plan_s* p) {
       } else if (tree_fwd_kg_supported(p->n0, p->n1, (int)kg)) {
         p->tree_kg = (int32_t)kg;
         p->tree_slab = (int32_t)slab;
+        p->tree_wpc = (int32_t)wpc;
       }
     } else if (p->kind == 1 && kind == "batched") {
       auto it = p->bs->cfg.find({(int)n0, (int)n1});
