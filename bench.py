@@ -34,8 +34,11 @@ if ROOT not in sys.path:
 
 METRIC = "SWDFT coeffs/s + % HBM roofline, FP32 tree vs plain FP64 direct @ rel err≤1e-5"
 PEAK_HBM_GBS = 8000.0
+# the kernel and the host code that picks its launch shape (tile, occupancy cap)
 KERNEL_SOURCES = ["paper_1707_08213_amd/csrc/tree_fwd_kernel.h",
-                  "paper_1707_08213_amd/csrc/tree_fwd_n16_r.hip"]
+                  "paper_1707_08213_amd/csrc/tree_fwd_n16_r.hip",
+                  "paper_1707_08213_amd/csrc/tree_fwd.hip",
+                  "paper_1707_08213_amd/csrc/tree_config.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tree_fwd_sin1024_traffic.json")
 
 
@@ -97,7 +100,7 @@ def pmc_summary(fetch_db: str, write_db: str, copy_bytes: int, out_json: str) ->
         rb, wb = f * f_scale * 1024, w * w_scale * 1024
         short = name.replace("(anonymous namespace)", "anon").split("(")[0][:60]
         lines.append(f"| {short} | {len(c['FETCH_SIZE'])} | {f:.1f} | {w:.1f} | {rb:.4g} | {wb:.4g} |")
-        if "tree_fwd_kernel<16, 16, true>" in name:
+        if "tree_fwd_kernel<16, 16, true" in name:
             tree_bytes = rb + wb
     lines.append("")
     lines.append(f"copy reference: {copy_bytes} B read and written; scale FETCH x{f_scale:.4f}, "
@@ -108,6 +111,31 @@ def pmc_summary(fetch_db: str, write_db: str, copy_bytes: int, out_json: str) ->
                        "kernel_hash": kernel_hash(), "hbm_bytes_per_launch": tree_bytes,
                        "fetch_scale": f_scale, "write_scale": w_scale}, fh, indent=1)
             fh.write("\n")
+    return "\n".join(lines)
+
+
+def trace_summary(db: str) -> str:
+    """Per-kernel duration table (markdown) from a rocprofv3 --kernel-trace
+    database, one row per kernel and grid size."""
+    import collections
+    import sqlite3
+    import statistics
+    con = sqlite3.connect(db)
+    durs = collections.defaultdict(list)
+    meta = {}
+    for name, dur, gx, wx, lds in con.execute(
+            "select name, duration, grid_x, workgroup_x, lds_size from kernels"):
+        short = name.replace("(anonymous namespace)", "anon").split("(")[0].replace("void ", "")
+        key = (short, gx // max(wx, 1))
+        durs[key].append(dur / 1000.0)
+        meta[key] = (wx, lds)
+    con.close()
+    lines = ["| kernel | calls | avg us | min us | max us | workgroups x size | LDS B |",
+             "|---|---|---|---|---|---|---|"]
+    for key, v in sorted(durs.items(), key=lambda kv: -sum(kv[1])):
+        wx, lds = meta[key]
+        lines.append(f"| {key[0][:75]} | {len(v)} | {statistics.mean(v):.1f} | {min(v):.1f} | "
+                     f"{max(v):.1f} | {key[1]} x {wx} | {lds} |")
     return "\n".join(lines)
 
 
@@ -448,7 +476,12 @@ def main() -> int:
                          "hardware byte counters)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="summarise two rocprofv3 --pmc databases and exit (no GPU needed)")
+    ap.add_argument("--trace-summary", metavar="TRACE_DB",
+                    help="summarise a rocprofv3 --kernel-trace database and exit (no GPU needed)")
     args = ap.parse_args()
+    if args.trace_summary:
+        print(trace_summary(args.trace_summary))
+        return 0
     if args.pmc_summary:
         # copy size = output bytes of the sin1024 workload (1009*1009*256 complex64)
         print(pmc_summary(args.pmc_summary[0], args.pmc_summary[1], 1009 * 1009 * 256 * 8,
@@ -456,7 +489,7 @@ def main() -> int:
         return 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
-              "(the transform shards over window rows with no exchange; see the design notes)",
+              "(the transform shards over window rows with no exchange between GPUs)",
               file=sys.stderr)
         return 2
 

@@ -196,9 +196,10 @@ swdft_status_t swdft2d_plan_batched(swdft2d_plan_t* out, const swdft2d_desc_t* d
 swdft_status_t swdft2d_tune(swdft2d_plan_t plan, const void* x, void* y, hipStream_t stream);
 
 /* Measurement aid (not part of the transform): fill `bytes` bytes at y
- * (8-byte aligned, bytes a multiple of 8) with a constant using the same
- * store width and cache policy as the tree's output path. Timing it gives the
- * empirical HBM write ceiling at a given byte count. */
+ * (8-byte aligned, bytes a multiple of 8) with a constant, with the access
+ * pattern of a device memset (16-byte stores, 256 workgroups sweeping the
+ * buffer front to back). Timing it gives the empirical HBM write ceiling at a
+ * given byte count. */
 swdft_status_t swdft2d_write_probe(void* y, int64_t bytes, hipStream_t stream);
 
 #ifdef __cplusplus

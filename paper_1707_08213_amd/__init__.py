@@ -308,7 +308,7 @@ class SWDFT2dFn(torch.autograd.Function):
 
 
 def write_probe(buf: torch.Tensor, nbytes: int | None = None) -> None:
-    """Fill buf with the tree's store pattern (HBM write-ceiling probe)."""
+    """Fill buf with a constant using a memset-like pattern (HBM write-ceiling probe)."""
     if not buf.is_cuda or not buf.is_contiguous():
         raise ValueError("probe buffer must be a contiguous cuda tensor")
     nbytes = buf.numel() * buf.element_size() if nbytes is None else nbytes

@@ -61,7 +61,7 @@ class SwdftError(RuntimeError):
 def _load():
     if not os.path.exists(LIBRARY):
         raise ImportError(
-            f"{LIBRARY} is missing: build it with `python -m paper_1707_08213_amd.build` "
+            f"{LIBRARY} is missing: build it with `python paper_1707_08213_amd/build.py` "
             "(the HIP library is required; there is no CPU fallback)")
     lib = ctypes.CDLL(LIBRARY)
     for name, (res, args) in SIGNATURES.items():

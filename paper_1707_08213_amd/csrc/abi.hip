@@ -116,131 +116,6 @@ swdft_algo_t resolve_algo(const swdft2d_plan_s* p) {
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-int env_int(const char* name, int fallback) {
-  const char* e = std::getenv(name);
-  return e && *e ? std::atoi(e) : fallback;
-}
-
-// Attribute of the current device, cached per device; 0 when there is none.
-int device_attr(hipDeviceAttribute_t attr, int (&cache)[64]) {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
-  if (cache[dev] == 0) {
-    int v = 0;
-    if (hipDeviceGetAttribute(&v, attr, dev) != hipSuccess || v <= 0) v = -1;
-    cache[dev] = v;
-  }
-  return cache[dev] > 0 ? cache[dev] : 0;
-}
-
-int lds_per_cu() {
-  static int cache[64] = {};
-  return device_attr(hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, cache);
-}
-
-int cu_count() {
-  static int cache[64] = {};
-  return device_attr(hipDeviceAttributeMultiprocessorCount, cache);
-}
-
-int32_t tree_kg(const swdft2d_plan_s* p) {
-  int kg = p->tree_kg > 0 ? p->tree_kg : env_int("SWDFT_TREE_KG", 0);
-  if (kg <= 0 || !swdft::tree_fwd_kg_supported(p->n0, p->n1, kg))
-    kg = swdft::tree_fwd_default_kg(p->n0, p->n1);
-  return kg;
-}
-
-// Slab count that fills the rounds of `slots` resident waves to at least 90%
-// with `columns` strips (at most 8 slabs), or 0 if none does.
-int64_t filling_slabs(int64_t columns, int64_t slots) {
-  for (int64_t s = 1; s <= 8; ++s) {
-    const int64_t tiles = columns * s;
-    if (tiles * 10 >= ceil_div(tiles, slots) * slots * 9) return s;
-  }
-  return 0;
-}
-
-// Resident-wave cap per CU (0 = none) and the slab count that goes with it.
-// With one wave per CU, unsplit n0 = 16 streams and a wave per column of its
-// strip, the resident waves write one narrow band of output rows that moves
-// down the image, which the HBM3E stacks absorb at close to the copy rate;
-// with many resident waves the store streams of many tiles interleave and
-// the write rate drops by 10-15% (measured on gfx950). The cap is only worth
-// it when the rounds of resident waves are nearly full.
-struct TreeCap {
-  int wpc = 0;
-  int64_t slabs = 0;  // 0: slab length from the uncapped rule
-};
-
-TreeCap tree_cap(const swdft2d_plan_s* p, int kg) {
-  const int64_t columns =
-      ceil_div(p->P1, swdft::tree_fwd_columns_per_wave(p->n0, p->n1, kg)) * p->batch;
-  const int64_t ncu = cu_count() > 0 ? cu_count() : 256;
-  TreeCap c;
-  c.wpc = p->tree_wpc >= 0 ? p->tree_wpc : env_int("SWDFT_TREE_WPC", -1);
-  if (c.wpc < 0) {
-    c.wpc = 0;
-    if (p->n0 == 16 && kg == 1) {
-      const int64_t s = filling_slabs(columns, ncu);
-      if (s > 0) c = TreeCap{1, s};
-    }
-    return c;
-  }
-  c.wpc = std::min(c.wpc, 8);
-  if (c.wpc > 0) c.slabs = std::max<int64_t>(1, filling_slabs(columns, ncu * c.wpc));
-  return c;
-}
-
-// Output rows per wave of the fused tree: P0 / slabs for a capped launch;
-// otherwise enough tiles (about 4096) to fill the chip several times over,
-// with slabs long enough that the n0-1 priming rows at the top of each stay a
-// small fraction of the work.
-int32_t tree_slab(const swdft2d_plan_s* p, int kg, const TreeCap& cap) {
-  const int cr = swdft::tree_fwd_rows_per_chunk(p->n0, p->n1, kg);
-  const int64_t nstrips = ceil_div(p->P1, swdft::tree_fwd_columns_per_wave(p->n0, p->n1, kg));
-  int64_t S = p->tree_slab > 0 ? p->tree_slab : env_int("SWDFT_TREE_SLAB", 0);
-  if (S <= 0) {
-    if (cap.wpc > 0 && cap.slabs > 0) {
-      S = ceil_div(p->P0, cap.slabs);
-    } else {
-      S = ceil_div(p->P0 * nstrips * p->batch, 4096);
-      S = std::max<int64_t>(S, 4 * (int64_t)(p->n0 - 1));
-    }
-  }
-  S = std::max<int64_t>(S, cr);
-  S = ceil_div(S, cr) * cr;
-  S = std::min<int64_t>(S, ceil_div(p->P0, cr) * cr);
-  return (int32_t)S;
-}
-
-swdft::TreeGeom tree_geom(const swdft2d_plan_s* p) {
-  swdft::TreeGeom g{};
-  g.N0 = p->N0;
-  g.N1 = p->N1;
-  g.P0 = p->P0;
-  g.P1 = p->P1;
-  g.x_image_stride = p->N0 * p->N1;
-  g.y_image_stride = p->P0 * p->P1 * p->n0 * p->n1;
-  g.kg = tree_kg(p);
-  const TreeCap cap = tree_cap(p, g.kg);
-  g.wpc = cap.wpc;
-  g.S = tree_slab(p, g.kg, cap);
-  g.nstrips = (int32_t)ceil_div(p->P1, swdft::tree_fwd_columns_per_wave(p->n0, p->n1, g.kg));
-  g.nslabs = (int32_t)ceil_div(p->P0, g.S);
-  g.batch = (int32_t)p->batch;
-  g.scale = norm_scale(p->norm, p->n0, p->n1);
-  g.lds_cu = lds_per_cu();
-  // With a cap and more tiles than one round of resident waves, tiles run in
-  // dispatch order so that each round covers one contiguous range of strips;
-  // otherwise each XCD takes a contiguous range (neighbouring strips share
-  // input columns in that XCD's L2).
-  const int64_t tiles = (int64_t)g.nstrips * g.nslabs * g.batch;
-  const int64_t resident = (int64_t)swdft::tree_fwd_resident_waves(g.wpc, cu_count());
-  g.order = (g.wpc > 0 && resident > 0 && tiles > resident) ? 1 : 0;
-  if (g.lds_cu <= 0) g.wpc = 0;
-  return g;
-}
-
 // dx rows per wave of the adjoint: a whole image column when that already
 // gives enough waves (no dy row is then read twice); otherwise slabs, each
 // primed by the n0-1 window rows below it.

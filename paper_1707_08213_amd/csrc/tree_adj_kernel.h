@@ -106,9 +106,12 @@ __device__ __forceinline__ void row_levels_adj(float2 (&v)[N1W], const float2* w
   });
 }
 
-__device__ __forceinline__ float2 load_nt(const float2* p) {
-  const f2v t = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(p));
-  return make_float2(t.x, t.y);
+// Non-temporal 8-byte load at byte offset off of a buffer resource; zero past
+// its end.
+__device__ __forceinline__ float2 load_buf_nt(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  constexpr int kNonTemporal = 2;
+  const u2v t = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, kNonTemporal);
+  return make_float2(__uint_as_float(t.x), __uint_as_float(t.y));
 }
 
 template <int N0W, int N1W>
@@ -156,10 +159,14 @@ __global__ __launch_bounds__(64) void tree_adj_kernel(const float2* __restrict__
   // column-phase roles
   const int cp_c = lane / N1W;
   const int cp_k1 = lane % N1W;
-  const int64_t cp_q1 = q1_0 + cp_c;
-  const bool cp_ok = cp_q1 < g.P1;
-  const float2* dycol = dyimg + cp_q1 * (N0W * N1W) + cp_k1;
+  // dy of one window row of the strip: QW windows from dystrip + q0 *
+  // y_row_stride, of which the first strip_bytes exist; lanes past the right
+  // edge read zero through the buffer resource's range check
+  const float2* dystrip = dyimg + q1_0 * (N0W * N1W);
   const int64_t y_row_stride = g.P1 * (N0W * N1W);
+  const uint32_t strip_bytes =
+      (uint32_t)(min((int64_t)C::QW, g.P1 - q1_0) * (N0W * N1W * (int)sizeof(float2)));
+  const uint32_t lane_off = (uint32_t)((cp_c * (N0W * N1W) + cp_k1) * (int)sizeof(float2));
   // row-phase roles
   const int rp_r = lane / C::QW;
   const int rp_c = lane % C::QW;
@@ -169,13 +176,14 @@ __global__ __launch_bounds__(64) void tree_adj_kernel(const float2* __restrict__
     sfor<0, C::RING>([&](auto K) { ring[L][K] = make_float2(0.f, 0.f); });
   });
 
+  // rows without a window of this slab get an empty resource (all zeros)
   auto load_step = [&](int64_t gstep, float2 (&dst)[N0W]) {
     const int64_t p = p_top - gstep;
     const int64_t q0 = p - (N0W - 1);
-    const bool ok = cp_ok && q0 >= 0 && q0 <= q0_last && p >= r0;
-    const float2* src = dycol + q0 * y_row_stride;
+    const bool ok = q0 >= 0 && q0 <= q0_last && p >= r0;
+    const auto rs = buf_rsrc(dystrip + (ok ? q0 : 0) * y_row_stride, ok ? strip_bytes : 0u);
     sfor<0, N0W>([&](auto K) {
-      dst[K] = ok ? load_nt(src + K * N1W) : make_float2(0.f, 0.f);
+      dst[K] = load_buf_nt(rs, lane_off + K * N1W * (int)sizeof(float2));
     });
   };
 

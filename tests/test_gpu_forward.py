@@ -201,8 +201,9 @@ def test_binding_rejects_bad_tensors(swd):
     assert e.value.name == "SWDFT_E_ALIGN"
 
 
-@pytest.mark.parametrize("n0,n1,kg", [(8, 1, 2), (8, 8, 2), (16, 16, 2), (16, 4, 2), (32, 8, 1),
-                                      (32, 32, 1), (32, 2, 2), (16, 32, 2)],
+@pytest.mark.parametrize("n0,n1,kg", [(8, 1, 2), (8, 8, 2), (8, 8, 1), (16, 16, 2), (16, 4, 2),
+                                      (16, 8, 1), (32, 8, 1), (32, 32, 1), (32, 2, 2), (16, 32, 2),
+                                      (8, 32, 1)],
                          ids=lambda v: str(v))
 def test_tree_split_streams(swd, orc, n0, n1, kg):
     """Column streams split over kg lanes by k0 residue (per-lane twiddle
@@ -216,3 +217,75 @@ def test_tree_split_streams(swd, orc, n0, n1, kg):
     finally:
         del os.environ["SWDFT_TREE_KG"]
     assert rel_err(y, orc.swdft2d(x.astype(np.complex128), n0, n1)) <= TOL_F32
+
+
+def _with_env(env, fn):
+    import os
+    saved = {k: os.environ.get(k) for k in env}
+    os.environ.update({k: str(v) for k, v in env.items()})
+    try:
+        return fn()
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+@pytest.mark.parametrize("N0,N1,n0,n1,cplx,batch,env", [
+    (70, 300, 16, 16, True, 3, {"SWDFT_TREE_WPC": 2}),
+    (50, 200, 8, 8, False, 1, {"SWDFT_TREE_WPC": 1, "SWDFT_TREE_KG": 1}),
+    (61, 150, 32, 8, False, 2, {"SWDFT_TREE_WPC": 1}),
+    (90, 260, 16, 16, False, 1, {"SWDFT_TREE_WPC": 0, "SWDFT_TREE_SLAB": 16}),
+], ids=["c16x16-b3-cap2", "r8x8-cap1-kg1", "r32x8-b2-cap1", "r16x16-nocap-slab16"])
+def test_tree_resident_cap(swd, orc, N0, N1, n0, n1, cplx, batch, env):
+    """Launches capped at one or two resident waves per CU (padding LDS) and
+    uncapped ones compute the same transform."""
+    gen = workloads.normal_complex if cplx else workloads.normal_real
+    xs = np.stack([gen((N0, N1), seed=N0 + N1 + b) for b in range(batch)])
+    dt = torch.complex64 if cplx else torch.float32
+
+    def run():
+        p = swd.Plan(N0, N1, n0, n1, dtype=dt, batch=batch)
+        print(f"[case] {p.describe()}", flush=True)
+        y = p.forward(torch.from_numpy(xs).cuda())
+        torch.cuda.synchronize()
+        return p.describe(), y.cpu().numpy()
+
+    desc, y = _with_env(env, run)
+    assert f"waves_per_cu={env['SWDFT_TREE_WPC']}" in desc
+    for b in range(batch):
+        ref = orc.swdft2d(xs[b].astype(np.complex128 if cplx else np.float64), n0, n1)
+        assert rel_err(y[b], ref) <= TOL_F32, b
+
+
+def test_tree_capped_dispatch_order_sampled(swd, orc):
+    """One resident wave per CU with more tiles than one round of waves: the
+    tiles run in dispatch order (rounds of contiguous strips)."""
+    N0, N1 = 120, 1100
+    x_np = workloads.normal_real((N0, N1), seed=77)
+
+    def run():
+        p = swd.Plan(N0, N1, 16, 16)
+        return p.describe(), sampled_check(swd, orc, x_np, 16, 16, 2048, 1004)
+
+    desc, (got, ref) = _with_env({"SWDFT_TREE_WPC": 1, "SWDFT_TREE_SLAB": 16}, run)
+    assert "waves_per_cu=1" in desc and "order=dispatch" in desc, desc
+    assert rel_err(got, ref) <= TOL_F32
+
+
+@pytest.mark.parametrize("offset,count", [(0, 1 << 20), (1, (1 << 20) + 1), (1, 7), (0, 1)],
+                         ids=["aligned", "head+tail", "short", "one"])
+def test_write_probe_fills_exactly(swd, offset, count):
+    """The write probe stores its constant into exactly the requested bytes,
+    including an unaligned head and an odd tail."""
+    buf = torch.zeros(count + 4, dtype=torch.complex64, device="cuda")
+    start = buf.data_ptr() + 8 * offset
+    from paper_1707_08213_amd import _lib
+    _lib.check(_lib.lib.swdft2d_write_probe(start, 8 * count, None), "swdft2d_write_probe")
+    torch.cuda.synchronize()
+    v = torch.view_as_real(buf).cpu().numpy()
+    inside = v[offset:offset + count]
+    assert np.all(inside[:, 0] == 1.0) and np.all(inside[:, 1] == -1.0)
+    assert np.all(v[:offset] == 0) and np.all(v[offset + count:] == 0)
