@@ -52,6 +52,8 @@ struct AdjGeom {
   int32_t nslabs;          // ceil(N0 / S)
   int32_t batch;
   float scale;
+  int32_t wpc;             // resident waves per CU: 0 = as many as fit, else capped
+  int32_t lds_cu;          // LDS bytes per CU (used to impose the cap)
 };
 
 // Geometry of one dense (matrix-core) launch: one wave owns 16/n1 window

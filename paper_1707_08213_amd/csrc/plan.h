@@ -109,6 +109,11 @@ void batched_build_tables(swdft2d_plan_s* p);
 void batched_free(BatchState* bs);
 int batched_default_slab(int n0, int n1, bool dense);
 
+// device and environment queries (tree_config.hip)
+int env_int(const char* name, int fallback);  // fallback when unset or empty
+int lds_per_cu();                             // LDS bytes per CU of the current device, 0 if none
+int cu_count();                               // CUs of the current device, 0 if none
+
 // tuning cache (tune.hip)
 void apply_cached_tuning(swdft2d_plan_s* p);
 

@@ -292,7 +292,10 @@ template <int N0W, int N1W, bool REAL>
 hipError_t launch_adj_one(const float2* dy, void* ws, void* dx, const AdjGeom& g,
                           const TwiddlesF32& tw, hipStream_t stream) {
   const int64_t nb = (int64_t)g.batch * g.nslabs * g.nstrips;
-  hipLaunchKernelGGL((tree_adj_kernel<N0W, N1W, REAL>), dim3((unsigned)nb), dim3(64), 0, stream,
+  using C = AdjCfg<N0W, N1W>;
+  const unsigned pad =
+      occupancy_lds(g.wpc, g.lds_cu, C::CR * C::ZROW * (unsigned)sizeof(float2));
+  hipLaunchKernelGGL((tree_adj_kernel<N0W, N1W, REAL>), dim3((unsigned)nb), dim3(64), pad, stream,
                      dy, ws, g, tw);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

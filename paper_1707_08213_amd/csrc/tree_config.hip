@@ -11,11 +11,6 @@ namespace host {
 
 namespace {
 
-int env_int(const char* name, int fallback) {
-  const char* e = std::getenv(name);
-  return e && *e ? std::atoi(e) : fallback;
-}
-
 // Attribute of the current device, cached per device; 0 when there is none.
 int device_attr(hipDeviceAttribute_t attr, int (&cache)[64]) {
   int dev = 0;
@@ -28,6 +23,13 @@ int device_attr(hipDeviceAttribute_t attr, int (&cache)[64]) {
   return cache[dev] > 0 ? cache[dev] : 0;
 }
 
+}  // namespace
+
+int env_int(const char* name, int fallback) {
+  const char* e = std::getenv(name);
+  return e && *e ? std::atoi(e) : fallback;
+}
+
 int lds_per_cu() {
   static int cache[64] = {};
   return device_attr(hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, cache);
@@ -37,6 +39,8 @@ int cu_count() {
   static int cache[64] = {};
   return device_attr(hipDeviceAttributeMultiprocessorCount, cache);
 }
+
+namespace {
 
 int32_t tree_kg(const swdft2d_plan_s* p) {
   int kg = p->tree_kg > 0 ? p->tree_kg : env_int("SWDFT_TREE_KG", 0);

@@ -149,7 +149,19 @@ struct ColCfg {
   static constexpr int ring_off(int u) { return u <= 1 ? 0 : ring_off(u - 1) + ring_size(u - 1); }
   static constexpr int RING_TOTAL = M0 > 0 ? ring_off(M0 + 1) : 1;
   static constexpr int OUTS = N0W / KG;  // outputs per lane and row
+  // twiddle index of node r + KG j at level u (u > G), without the lane part
+  static constexpr int tw_index(int u, int j) { return KG * j * (N0W >> u); }
+  // uniform twiddles other than 1 and -i; at a split level these are folded
+  // into a per-lane factor once per tile
+  static constexpr bool folded(int u, int j) {
+    return KG > 1 && u > G && tw_index(u, j) != 0 && 4 * tw_index(u, j) != N0W;
+  }
+  static constexpr int LW = N0W / 2 > 0 ? N0W / 2 : 1;  // held(u - 1) <= n0 / 2
 };
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
 
 // Column levels u = 1..m0 (Eq. (6)) for one new row p of a (q1, k1) stream:
 //   T_u[p][i]     = T_{u-1}[p - s_u][i] + Omega0[i s_u] T_{u-1}[p][i]
@@ -160,10 +172,13 @@ struct ColCfg {
 // For a split stream (KG > 1) the twiddle of node r + KG j is
 // Omega0[(r + KG j) s_u] = lanefac[u] * Omega0[KG j s_u]: a per-lane factor
 // (lanefac[u] = Omega0[(r mod 2^u) s_u]) times a twiddle uniform over the wave.
+// Where the uniform twiddle is not 1 or -i the product is precomputed per
+// lane (lw[u][j]), so every node costs one complex multiply.
 // emit(j, v) receives output k0 = r + KG j.
 template <int N0W, int KG, int ST, typename Emit>
 __device__ __forceinline__ void column_levels(float2 z, float2 (&ring)[ColCfg<N0W, KG>::RING_TOTAL],
                                               const float2 (&lanefac)[ColCfg<N0W, KG>::M0 + 1],
+                                              const float2 (&lw)[ColCfg<N0W, KG>::M0 + 1][ColCfg<N0W, KG>::LW],
                                               const float2* w0, Emit&& emit) {
   using CC = ColCfg<N0W, KG>;
   float2 cur[N0W];
@@ -187,11 +202,13 @@ __device__ __forceinline__ void column_levels(float2 z, float2 (&ring)[ColCfg<N0
         const float2 b = ring[base + j];
         float2 d = cur[j];
         ring[base + j] = d;
-        if constexpr (KG > 1) {
-          const float2 f = lanefac[u];
-          d = make_float2(f.x * d.x - f.y * d.y, f.x * d.y + f.y * d.x);
+        float2 t;
+        if constexpr (CC::folded(u, j)) {
+          t = cmul(lw[u][j], d);
+        } else {
+          if constexpr (KG > 1) d = cmul(lanefac[u], d);
+          t = twmul<KG * j * s, N0W>(d, w0);
         }
-        const float2 t = twmul<KG * j * s, N0W>(d, w0);
         if constexpr (u == CC::M0) {
           emit(std::integral_constant<int, j>{}, cadd(b, t));
           emit(std::integral_constant<int, j + hp>{}, csub(b, t));
@@ -354,6 +371,15 @@ __device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float
     }
   });
 
+  float2 lw[CC::M0 + 1][CC::LW];
+  sfor<1, CC::M0 + 1>([&](auto U) {
+    constexpr int u = U;
+    sfor<0, CC::LW>([&](auto J) {
+      constexpr int j = J;
+      if constexpr (CC::folded(u, j)) lw[u][j] = cmul(lanefac[u], uload(w0 + CC::tw_index(u, j)));
+    });
+  });
+
   float2 ring[CC::RING_TOTAL];
   sfor<0, CC::RING_TOTAL>([&](auto K) { ring[K] = make_float2(0.f, 0.f); });
 
@@ -412,7 +438,7 @@ __device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float
       if constexpr (N0W == 1) {
         store_buf_nt(out, lane_off, z);
       } else {
-        column_levels<N0W, KG, st % C::RING>(z, ring, lanefac, w0, [&](auto J, float2 v) {
+        column_levels<N0W, KG, st % C::RING>(z, ring, lanefac, lw, w0, [&](auto J, float2 v) {
           store_buf_nt(out, lane_off + (KG * J) * N1W * (int)sizeof(float2), v);
         });
       }
