@@ -184,8 +184,8 @@ swdft_status_t swdft2d_plan_batched(swdft2d_plan_t* out, const swdft2d_desc_t* d
                                     swdft_dtype_t dtype);
 
 /* Time candidate configurations on the caller's x and y and keep the fastest:
- * tree tile shapes (lanes per column stream, slab length, resident waves per
- * CU) and, when the
+ * tree tile shapes (lanes per column stream, slab length, resident
+ * workgroups per CU, waves per strip) and, when the
  * plan's algorithm is AUTO (or DENSE_BF16X2) and the window shape allows, the
  * dense matrix-core variant, which is admitted only if its output agrees with
  * the tree's to a normwise relative difference of 1e-5. Batched plans are

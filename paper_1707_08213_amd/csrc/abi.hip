@@ -467,11 +467,12 @@ swdft_status_t swdft2d_describe(swdft2d_plan_t plan, char* buf, int32_t len) {
     const swdft::TreeGeom g = tree_geom(p);
     snprintf(buf, (size_t)len,
              "algo=tree n=%dx%d N=%lldx%lld batch=%lld kg=%d cols_per_wave=%d rows_per_chunk=%d "
-             "slab=%d strips=%d slabs=%d waves=%lld waves_per_cu=%d order=%s",
+             "slab=%d strips=%d slabs=%d waves=%lld waves_per_strip=%d groups_per_cu=%d order=%s",
              p->n0, p->n1, (long long)p->N0, (long long)p->N1, (long long)p->batch, g.kg,
              swdft::tree_fwd_columns_per_wave(p->n0, p->n1, g.kg),
-             swdft::tree_fwd_rows_per_chunk(p->n0, p->n1, g.kg), g.S, g.nstrips, g.nslabs,
-             (long long)g.nstrips * g.nslabs * p->batch, g.wpc, g.order ? "dispatch" : "xcd");
+             swdft::tree_fwd_rows_per_chunk(p->n0, p->n1, g.kg, g.wv), g.S, g.nstrips, g.nslabs,
+             (long long)g.nstrips * g.nslabs * p->batch * g.wv, g.wv, g.wpc,
+             g.order ? "dispatch" : "xcd");
   } else if (a == SWDFT_ALGO_DENSE_BF16X2) {
     const swdft::DenseGeom g = dense_geom(p);
     snprintf(buf, (size_t)len,

@@ -38,7 +38,7 @@ struct TreeGeom {
   int32_t wpc;             // resident waves per CU: 0 = as many as fit, else capped
   int32_t lds_cu;          // LDS bytes per CU (used to impose the cap)
   int32_t order;           // tile order: 0 = a contiguous range per XCD, 1 = dispatch order
-  int32_t pad_;
+  int32_t wv;              // waves per workgroup sharing one strip, 1 or 2
 };
 
 // Geometry of one adjoint launch. One wave owns a strip of window columns and
@@ -84,10 +84,11 @@ struct DirectGeom {
 hipError_t launch_tree_fwd(int n0, int n1, bool real_input, const void* x, float2* y,
                            const TreeGeom& g, const TwiddlesF32& tw, hipStream_t stream);
 int tree_fwd_columns_per_wave(int n0, int n1, int kg);
-int tree_fwd_rows_per_chunk(int n0, int n1, int kg);
+int tree_fwd_rows_per_chunk(int n0, int n1, int kg, int wv = 1);
 // lanes per column stream used when the caller does not choose
 int tree_fwd_default_kg(int n0, int n1);
 bool tree_fwd_kg_supported(int n0, int n1, int kg);
+bool tree_fwd_wv_supported(int n0, int kg, int wv);
 int tree_fwd_resident_waves(int wpc, int ncu);
 
 hipError_t launch_tree_adj(int n0, int n1, bool real_input, const float2* dy, void* ws, void* dx,

@@ -68,7 +68,8 @@ struct swdft2d_plan_s {
   bool tuned = false;                         // tuned or read from the tuning cache
   int32_t tree_slab = 0;                      // 0 = choose automatically
   int32_t tree_kg = 0;                        // 0 = choose automatically
-  int32_t tree_wpc = -1;                      // resident waves per CU, -1 = automatic
+  int32_t tree_wpc = -1;                      // resident workgroups per CU, -1 = automatic
+  int32_t tree_wv = 0;                        // waves per strip (1 or 2), 0 = automatic
   int32_t dense_slab = 0;                     // 0 = choose automatically
   swdft::TwiddlesF32 tw32{};
   swdft::TwiddlesF64 tw64{};

@@ -71,6 +71,16 @@ struct TreeCap {
   int64_t slabs = 0;  // 0: slab length from the uncapped rule
 };
 
+// Shapes whose default is one workgroup per CU (measured on gfx950): unsplit
+// n0 = 16 streams with one wave per strip (n1 >= 16), and split streams of
+// n1 = 8 windows (n0 >= 16) with two waves per strip. Other combinations
+// were not faster than the uncapped launch.
+bool capped_by_default(int n0, int n1, int kg) {
+  return (n0 == 16 && kg == 1) || (n0 >= 16 && n1 == 8 && kg == 2);
+}
+
+bool two_waves_by_default(int n0, int n1, int kg) { return n0 >= 16 && n1 == 8 && kg == 2; }
+
 TreeCap tree_cap(const swdft2d_plan_s* p, int kg) {
   const int64_t columns =
       ceil_div(p->P1, swdft::tree_fwd_columns_per_wave(p->n0, p->n1, kg)) * p->batch;
@@ -79,7 +89,7 @@ TreeCap tree_cap(const swdft2d_plan_s* p, int kg) {
   c.wpc = p->tree_wpc >= 0 ? p->tree_wpc : env_int("SWDFT_TREE_WPC", -1);
   if (c.wpc < 0) {
     c.wpc = 0;
-    if (p->n0 == 16 && kg == 1) {
+    if (capped_by_default(p->n0, p->n1, kg)) {
       const int64_t s = filling_slabs(columns, ncu);
       if (s > 0) c = TreeCap{1, s};
     }
@@ -90,12 +100,23 @@ TreeCap tree_cap(const swdft2d_plan_s* p, int kg) {
   return c;
 }
 
+// Waves per workgroup sharing a strip: two for capped n1 = 8 split streams
+// (one wave's issue rate would bound the tile: 1024x1024 / 16x8 went from 5.5
+// to 6.7-6.9 TB/s, 2048x512 / 32x8 from 5.4 to 5.55); one otherwise (for
+// unsplit n0 = 16 streams a second wave lowered the write rate by 11%).
+int32_t tree_wv(const swdft2d_plan_s* p, int kg, int wpc) {
+  int wv = p->tree_wv > 0 ? p->tree_wv : env_int("SWDFT_TREE_WV", 0);
+  if (wv <= 0) wv = (wpc == 1 && two_waves_by_default(p->n0, p->n1, kg)) ? 2 : 1;
+  if (!swdft::tree_fwd_wv_supported(p->n0, kg, wv)) wv = 1;
+  return wv;
+}
+
 // Output rows per wave of the fused tree: P0 / slabs for a capped launch;
 // otherwise enough tiles (about 4096) to fill the chip several times over,
 // with slabs long enough that the n0-1 priming rows at the top of each stay a
 // small fraction of the work.
-int32_t tree_slab(const swdft2d_plan_s* p, int kg, const TreeCap& cap) {
-  const int cr = swdft::tree_fwd_rows_per_chunk(p->n0, p->n1, kg);
+int32_t tree_slab(const swdft2d_plan_s* p, int kg, int wv, const TreeCap& cap) {
+  const int cr = swdft::tree_fwd_rows_per_chunk(p->n0, p->n1, kg, wv);
   const int64_t nstrips = ceil_div(p->P1, swdft::tree_fwd_columns_per_wave(p->n0, p->n1, kg));
   int64_t S = p->tree_slab > 0 ? p->tree_slab : env_int("SWDFT_TREE_SLAB", 0);
   if (S <= 0) {
@@ -125,7 +146,8 @@ swdft::TreeGeom tree_geom(const swdft2d_plan_s* p) {
   g.kg = tree_kg(p);
   const TreeCap cap = tree_cap(p, g.kg);
   g.wpc = cap.wpc;
-  g.S = tree_slab(p, g.kg, cap);
+  g.wv = tree_wv(p, g.kg, g.wpc);
+  g.S = tree_slab(p, g.kg, g.wv, cap);
   g.nstrips = (int32_t)ceil_div(p->P1, swdft::tree_fwd_columns_per_wave(p->n0, p->n1, g.kg));
   g.nslabs = (int32_t)ceil_div(p->P0, g.S);
   g.batch = (int32_t)p->batch;

@@ -8,9 +8,9 @@ int tree_fwd_columns_per_wave(int n0, int n1, int kg) {
   return 64 / (n1 * kg);
 }
 
-int tree_fwd_rows_per_chunk(int n0, int n1, int kg) {
+int tree_fwd_rows_per_chunk(int n0, int n1, int kg, int wv) {
   const int ring = n0 > 1 ? n0 / 2 : 1;
-  const int rows_per_pass = n1 * kg;
+  const int rows_per_pass = n1 * kg * wv;
   return rows_per_pass > ring ? rows_per_pass : ring;
 }
 
@@ -24,6 +24,10 @@ int tree_fwd_default_kg(int n0, int n1) {
 }
 
 int tree_fwd_resident_waves(int wpc, int ncu) { return wpc > 0 && ncu > 0 ? wpc * ncu : 0; }
+
+bool tree_fwd_wv_supported(int n0, int kg, int wv) {
+  return wv == 1 || (wv == 2 && tree::tree_has_wv2(n0, kg));
+}
 
 bool tree_fwd_kg_supported(int n0, int n1, int kg) {
   return kg == 1 || (kg == 2 && n0 >= 8 && n1 <= 32);

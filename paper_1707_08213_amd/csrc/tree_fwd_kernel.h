@@ -276,17 +276,23 @@ __device__ __forceinline__ int xcd_tile(int id, int nb) {
   return x < r ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
 }
 
-template <int N0W, int N1W, bool REAL, int KG>
+// Tile shape. KG lanes of a wave split a column stream by k0 residue; WV
+// waves of a workgroup share one strip and split it further (residue
+// r = lane residue + KG * wave), so KT = KG * WV. Each wave computes the
+// row phase for CR / WV of the chunk's rows.
+template <int N0W, int N1W, bool REAL, int KG, int WV = 1>
 struct TreeCfg {
   static constexpr int M0 = ilog2(N0W);
-  static constexpr int QW = 64 / (N1W * KG);                // window columns per wave
-  static constexpr int R = 64 / QW;                         // rows per row pass
+  static constexpr int KT = KG * WV;                        // total split of a stream
+  static constexpr int QW = 64 / (N1W * KG);                // window columns per strip
+  static constexpr int R = 64 / QW;                         // rows per row pass of a wave
   static constexpr int RING = N0W > 1 ? N0W / 2 : 1;        // ring period
-  static constexpr int CR = R > RING ? R : RING;            // rows per chunk
+  static constexpr int CR = R * WV > RING ? R * WV : RING;  // rows per chunk
+  static constexpr int PPW = CR / (R * WV);                 // row passes per wave and chunk
   static constexpr int ZS = N1W + 1;                        // padded stride of one window column in LDS
   static constexpr int ZROW = QW * ZS;                      // float2 per chunk row in LDS
   static constexpr int LDS_FLOAT2 = CR * ZROW;
-  static_assert(KG == 1 || KG < N0W, "a split stream needs KG < n0");
+  static_assert(KT == 1 || KT < N0W, "a split stream needs KG * WV < n0");
   static_assert(N1W * KG <= 64, "one wave must hold a whole window column");
 };
 
@@ -294,14 +300,15 @@ struct TreeCfg {
 // rows [slab*S, +S) of image b. w0, w1 point at the twiddle vectors (kernel
 // arguments or a device table); zl is the wave's LDS buffer of
 // TreeCfg::LDS_FLOAT2 elements.
-template <int N0W, int N1W, bool REAL, int KG>
+template <int N0W, int N1W, bool REAL, int KG, int WV = 1>
 __device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float2* __restrict__ y,
                                               const TreeGeom& g_in, const float2* __restrict__ w0,
                                               const float2* __restrict__ w1, int strip, int slab,
                                               int b, float2* __restrict__ zl) {
-  using C = TreeCfg<N0W, N1W, REAL, KG>;
-  using CC = ColCfg<N0W, KG>;
-  const int lane = threadIdx.x;
+  using C = TreeCfg<N0W, N1W, REAL, KG, WV>;
+  using CC = ColCfg<N0W, C::KT>;
+  const int lane = threadIdx.x % 64;
+  const int wv = WV > 1 ? __builtin_amdgcn_readfirstlane((int)threadIdx.x / 64) : 0;
   const TreeGeom g = uniform_copy(g_in);
 
   const int64_t q1_0 = (int64_t)strip * C::QW;
@@ -327,27 +334,30 @@ __device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float
     const int64_t col = rp_q1 + (N1W - 1 - d);
     x_off[d] = col < g.N1 ? (uint32_t)(((int64_t)rp_r * g.N1 + col) * EB) : kOutOfRange;
   });
-  // Raw inputs of one chunk (CR rows from crow), loaded a chunk ahead so that
-  // their latency hides behind the column phase of the previous chunk. Rows
-  // past the image bottom lie outside the resource and read zero.
-  constexpr int PASSES = C::CR / C::R;
+  // Raw inputs of this wave's passes of one chunk (rows crow + (wv * PPW +
+  // ps) * R + r), loaded a chunk ahead so that their latency hides behind the
+  // column phase of the previous chunk. Rows past the image bottom lie
+  // outside the resource and read zero.
+  constexpr int PASSES = C::PPW;
   XT xin[PASSES][N1W];
   auto load_chunk = [&](int64_t crow) {
     const int64_t rows = min((int64_t)C::CR, g.N0 - crow);
     const auto rs = buf_rsrc(ximg + (rows > 0 ? crow : 0) * g.N1,
                              rows > 0 ? (uint32_t)(rows * g.N1 * EB) : 0u);
+    const uint32_t wave_off = (uint32_t)(wv * C::PPW * C::R * g.N1 * EB);
     sfor<0, PASSES>([&](auto PS) {
       constexpr int ps = PS;
       sfor<0, N1W>([&](auto D) {
         constexpr int d = D;
-        xin[ps][d] = load_buf<REAL>(rs, x_off[d] + (uint32_t)(ps * C::R * g.N1 * EB));
+        xin[ps][d] = load_buf<REAL>(rs, x_off[d] + wave_off + (uint32_t)(ps * C::R * g.N1 * EB));
       });
     });
   };
 
-  // column-phase roles: lane (c, res, k1)
+  // column-phase roles: lane (c, res, k1); the stream residue is shared
+  // between the lane (KG) and the wave (WV)
   const int cp_c = lane / (N1W * KG);
-  const int cp_res = (lane / N1W) % KG;
+  const int cp_res = (lane / N1W) % KG + KG * wv;
   const int cp_k1 = lane % N1W;
   // Output of one row of the strip: QW windows of n0*n1 values from ystrip +
   // q0 * y_row_stride; only the first strip_bytes exist (the last strip of a
@@ -363,7 +373,7 @@ __device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float
   lanefac[0] = make_float2(1.f, 0.f);
   sfor<1, CC::M0 + 1>([&](auto U) {
     constexpr int u = U;
-    if constexpr (KG > 1) {
+    if constexpr (C::KT > 1) {
       const int idx = (cp_res & ((1 << u) - 1)) * (N0W >> u);
       lanefac[u] = w0[idx];
     } else {
@@ -401,7 +411,7 @@ __device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float
       if (g.scale != 1.0f) {
         sfor<0, N1W>([&](auto K) { v[K] = make_float2(v[K].x * g.scale, v[K].y * g.scale); });
       }
-      float2* zrow = zl + (ps * C::R + rp_r) * C::ZROW + rp_c * C::ZS;
+      float2* zrow = zl + ((wv * C::PPW + ps) * C::R + rp_r) * C::ZROW + rp_c * C::ZS;
       sfor<0, N1W>([&](auto K) { zrow[K] = v[K]; });
     });
   };
@@ -438,8 +448,8 @@ __device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float
       if constexpr (N0W == 1) {
         store_buf_nt(out, lane_off, z);
       } else {
-        column_levels<N0W, KG, st % C::RING>(z, ring, lanefac, lw, w0, [&](auto J, float2 v) {
-          store_buf_nt(out, lane_off + (KG * J) * N1W * (int)sizeof(float2), v);
+        column_levels<N0W, C::KT, st % C::RING>(z, ring, lanefac, lw, w0, [&](auto J, float2 v) {
+          store_buf_nt(out, lane_off + (C::KT * J) * N1W * (int)sizeof(float2), v);
         });
       }
     });
@@ -451,48 +461,62 @@ __device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float
   }
 }
 
-template <int N0W, int N1W, bool REAL, int KG>
-__global__ __launch_bounds__(64) void tree_fwd_kernel(const void* __restrict__ xv,
-                                                      float2* __restrict__ y, TreeGeom g,
-                                                      TwiddlesF32 tw) {
-  using C = TreeCfg<N0W, N1W, REAL, KG>;
+template <int N0W, int N1W, bool REAL, int KG, int WV>
+__global__ __launch_bounds__(64 * WV) void tree_fwd_kernel(const void* __restrict__ xv,
+                                                           float2* __restrict__ y, TreeGeom g,
+                                                           TwiddlesF32 tw) {
+  using C = TreeCfg<N0W, N1W, REAL, KG, WV>;
   __shared__ float2 zl[C::LDS_FLOAT2];
   int id = g.order ? (int)blockIdx.x : xcd_tile(blockIdx.x, gridDim.x);
   const int strip = id % g.nstrips;
   id /= g.nstrips;
   const int slab = id % g.nslabs;
   const int b = id / g.nslabs;
-  tree_fwd_tile<N0W, N1W, REAL, KG>(xv, y, g, tw.w0, tw.w1, strip, slab, b, zl);
+  tree_fwd_tile<N0W, N1W, REAL, KG, WV>(xv, y, g, tw.w0, tw.w1, strip, slab, b, zl);
 }
 
-// Dynamic LDS that caps the resident waves per CU at wpc (one wave per
-// workgroup): the workgroup's total LDS is set midway between lds_cu/(wpc+1)
-// and lds_cu/wpc. The kernel does not touch it.
+// Dynamic LDS that caps the resident workgroups per CU at wpc: the
+// workgroup's total LDS is set midway between lds_cu/(wpc+1) and
+// lds_cu/wpc. The kernel does not touch it.
 inline unsigned occupancy_lds(int wpc, int lds_cu, unsigned static_lds) {
   if (wpc <= 0 || lds_cu <= 0) return 0u;
   const unsigned want = (unsigned)(lds_cu / wpc + lds_cu / (wpc + 1)) / 2u;
   return want > static_lds ? want - static_lds : 0u;
 }
 
+// Two waves per strip exist for n0 >= 16 (where one wave per CU is the
+// default and the wave's issue rate bounds the tile).
+constexpr bool tree_has_wv2(int n0, int kg) { return n0 >= 16 && kg * 2 < n0; }
+
+template <int N0W, int N1W, bool REAL, int KG, int WV>
+hipError_t launch_cfg(const void* x, float2* y, const TreeGeom& g, const TwiddlesF32& tw,
+                      hipStream_t stream) {
+  const int64_t nb = (int64_t)g.batch * g.nslabs * g.nstrips;
+  const unsigned pad = occupancy_lds(
+      g.wpc, g.lds_cu, TreeCfg<N0W, N1W, REAL, KG, WV>::LDS_FLOAT2 * (unsigned)sizeof(float2));
+  hipLaunchKernelGGL((tree_fwd_kernel<N0W, N1W, REAL, KG, WV>), dim3((unsigned)nb), dim3(64 * WV),
+                     pad, stream, x, y, g, tw);
+  return hipGetLastError();
+}
+
+template <int N0W, int N1W, bool REAL, int KG>
+hipError_t launch_kg(const void* x, float2* y, const TreeGeom& g, const TwiddlesF32& tw,
+                     hipStream_t stream) {
+  if constexpr (tree_has_wv2(N0W, KG)) {
+    if (g.wv == 2) return launch_cfg<N0W, N1W, REAL, KG, 2>(x, y, g, tw, stream);
+  }
+  if (g.wv != 1) return hipErrorInvalidValue;
+  return launch_cfg<N0W, N1W, REAL, KG, 1>(x, y, g, tw, stream);
+}
+
 template <int N0W, int N1W, bool REAL>
 hipError_t launch_one(const void* x, float2* y, const TreeGeom& g, const TwiddlesF32& tw,
                       hipStream_t stream) {
-  const int64_t nb = (int64_t)g.batch * g.nslabs * g.nstrips;
   if constexpr (N0W >= 8 && N1W <= 32) {
-    if (g.kg == 2) {
-      const unsigned pad = occupancy_lds(
-          g.wpc, g.lds_cu, TreeCfg<N0W, N1W, REAL, 2>::LDS_FLOAT2 * (unsigned)sizeof(float2));
-      hipLaunchKernelGGL((tree_fwd_kernel<N0W, N1W, REAL, 2>), dim3((unsigned)nb), dim3(64), pad,
-                         stream, x, y, g, tw);
-      return hipGetLastError();
-    }
+    if (g.kg == 2) return launch_kg<N0W, N1W, REAL, 2>(x, y, g, tw, stream);
   }
   if (g.kg != 1) return hipErrorInvalidValue;
-  const unsigned pad = occupancy_lds(
-      g.wpc, g.lds_cu, TreeCfg<N0W, N1W, REAL, 1>::LDS_FLOAT2 * (unsigned)sizeof(float2));
-  hipLaunchKernelGGL((tree_fwd_kernel<N0W, N1W, REAL, 1>), dim3((unsigned)nb), dim3(64), pad, stream,
-                     x, y, g, tw);
-  return hipGetLastError();
+  return launch_kg<N0W, N1W, REAL, 1>(x, y, g, tw, stream);
 }
 
 // One translation unit per (n0, input type) instantiates launchers for every n1.

@@ -3,8 +3,9 @@
 //
 // swdft2d_tune times candidate configurations on the caller's buffers and
 // keeps the fastest. Candidates: the tree with 1 or 2 lanes per column stream,
-// slab lengths from a whole column down to about 4096 tiles, and resident
-// waves per CU uncapped, 1 or 2; and (where the shape allows and the plan's
+// slab lengths from a whole column down to about 4096 tiles, resident
+// workgroups per CU uncapped, 1 or 2, and one or two waves per strip; and
+// (where the shape allows and the plan's
 // algorithm is AUTO or DENSE) the dense matrix-core variant with two slab
 // lengths. The dense variant is admitted only if its output agrees with the
 // tree's to a normwise relative difference of 1e-5 on the first
@@ -14,7 +15,7 @@
 // Cache: when SWDFT_AUTOTUNE_CACHE names a file, results are appended to it as
 // one JSON object per line, and plans consult it at their first exec:
 //   {"arch":"gfx950","kind":"single","n0":16,"n1":16,"real":1,"size":20,
-//    "algo":"tree","kg":1,"slab":1024,"wpc":1,"us":317.1}
+//    "algo":"tree","kg":1,"slab":1024,"wpc":1,"wv":1,"us":317.1}
 // ("size" is floor(log2(windows per launch)); batched entries have
 // "kind":"batched" and no size). The last matching line wins.
 #include <algorithm>
@@ -37,7 +38,8 @@ struct Candidate {
   int kg = 1;
   int slab = 0;
   float us = 0.f;
-  int wpc = -1;  // tree: resident waves per CU (0 = no cap); -1 = automatic
+  int wpc = -1;  // tree: resident workgroups per CU (0 = no cap); -1 = automatic
+  int wv = 0;    // tree: waves per strip (1 or 2); 0 = automatic
 };
 
 std::string device_arch() {
@@ -171,9 +173,13 @@ swdft_status_t tune_single(swdft2d_plan_s* p, const void* x, void* y, hipStream_
         int64_t sl = ceil_div(std::max<int64_t>(s, cr), cr) * cr;
         sl = std::min<int64_t>(sl, ceil_div(p->P0, cr) * cr);
         for (int wpc : {0, 1, 2}) {
-          bool dup = false;
-          for (auto& c : cands) dup |= (!c.dense && c.kg == kg && c.slab == sl && c.wpc == wpc);
-          if (!dup) cands.push_back({false, kg, (int)sl, 0.f, wpc});
+          for (int wv : {1, 2}) {
+            if (!tree_fwd_wv_supported(p->n0, kg, wv)) continue;
+            bool dup = false;
+            for (auto& c : cands)
+              dup |= (!c.dense && c.kg == kg && c.slab == sl && c.wpc == wpc && c.wv == wv);
+            if (!dup) cands.push_back({false, kg, (int)sl, 0.f, wpc, wv});
+          }
         }
       }
     }
@@ -191,6 +197,7 @@ swdft_status_t tune_single(swdft2d_plan_s* p, const void* x, void* y, hipStream_
       p->tree_kg = c.kg;
       p->tree_slab = c.slab;
       p->tree_wpc = c.wpc;
+      p->tree_wv = c.wv;
     }
   };
   auto run = [&]() -> swdft_status_t {
@@ -237,10 +244,10 @@ swdft_status_t tune_single(swdft2d_plan_s* p, const void* x, void* y, hipStream_
   char line[512];
   std::snprintf(line, sizeof(line),
                 "{\"arch\":\"%s\",\"kind\":\"single\",\"n0\":%d,\"n1\":%d,\"real\":%d,\"size\":%d,"
-                "\"algo\":\"%s\",\"kg\":%d,\"slab\":%d,\"wpc\":%d,\"us\":%.1f}",
+                "\"algo\":\"%s\",\"kg\":%d,\"slab\":%d,\"wpc\":%d,\"wv\":%d,\"us\":%.1f}",
                 device_arch().c_str(), p->n0, p->n1, real ? 1 : 0,
                 size_class(p->P0 * p->P1 * p->batch), cands[best].dense ? "dense" : "tree",
-                cands[best].kg, cands[best].slab, cands[best].wpc, cands[best].us);
+                cands[best].kg, cands[best].slab, cands[best].wpc, cands[best].wv, cands[best].us);
   append_cache(line);
   return SWDFT_OK;
 }
@@ -337,7 +344,7 @@ void apply_cached_tuning(swdft2d_plan_s* p) {
   while (std::fgets(buf, sizeof(buf), f)) {
     const std::string s(buf);
     std::string a, kind, algo;
-    long long n0 = 0, n1 = 0, r = 0, size = -1, kg = 1, slab = 0, wpc = -1;
+    long long n0 = 0, n1 = 0, r = 0, size = -1, kg = 1, slab = 0, wpc = -1, wv = 0;
     if (!json_str(s, "arch", &a) || a != arch || !json_str(s, "kind", &kind) ||
         !json_str(s, "algo", &algo) || !json_int(s, "n0", &n0) || !json_int(s, "n1", &n1) ||
         !json_int(s, "real", &r) || (r != 0) != real)
@@ -345,6 +352,7 @@ void apply_cached_tuning(swdft2d_plan_s* p) {
     json_int(s, "kg", &kg);
     json_int(s, "slab", &slab);
     json_int(s, "wpc", &wpc);
+    json_int(s, "wv", &wv);
     const bool dense = algo == "dense";
     if (p->kind == 0 && kind == "single" && n0 == p->n0 && n1 == p->n1 &&
         json_int(s, "size", &size) && size == size_class(p->P0 * p->P1 * p->batch)) {
@@ -356,6 +364,7 @@ void apply_cached_tuning(swdft2d_plan_s* p) {
         p->tree_kg = (int32_t)kg;
         p->tree_slab = (int32_t)slab;
         p->tree_wpc = (int32_t)wpc;
+        p->tree_wv = (int32_t)wv;
       }
     } else if (p->kind == 1 && kind == "batched") {
       auto it = p->bs->cfg.find({(int)n0, (int)n1});

@@ -54,11 +54,13 @@ def test_batched_matches_oracle(swd, orc, cplx):
         assert rel_err(o, ref) <= TOL, (N0, N1, n0, n1)
 
 
-def test_batched_equals_single_plans_bitwise(swd):
+def test_batched_equals_single_plans_bitwise(swd, monkeypatch):
     """The tree classes run the same tile code as single-image plans with the
-    same lanes per stream: outputs must be bit-identical."""
+    same split of each column stream (lanes per stream, one wave per strip):
+    outputs must be bit-identical."""
     imgs = [torch.from_numpy(a).cuda() for a in make_images(SHAPES, 90)]
     outs = swd.swdft2d_batched(imgs, [(s[2], s[3]) for s in SHAPES])
+    monkeypatch.setenv("SWDFT_TREE_WV", "1")
     for im, s, o in zip(imgs, SHAPES, outs):
         single = swd.swdft2d(im, s[2], s[3])
         assert torch.equal(torch.view_as_real(o), torch.view_as_real(single)), s

@@ -238,10 +238,16 @@ def _with_env(env, fn):
     (50, 200, 8, 8, False, 1, {"SWDFT_TREE_WPC": 1, "SWDFT_TREE_KG": 1}),
     (61, 150, 32, 8, False, 2, {"SWDFT_TREE_WPC": 1}),
     (90, 260, 16, 16, False, 1, {"SWDFT_TREE_WPC": 0, "SWDFT_TREE_SLAB": 16}),
-], ids=["c16x16-b3-cap2", "r8x8-cap1-kg1", "r32x8-b2-cap1", "r16x16-nocap-slab16"])
+    (70, 300, 32, 8, True, 2, {"SWDFT_TREE_WPC": 1, "SWDFT_TREE_WV": 2}),
+    (45, 130, 16, 32, False, 1, {"SWDFT_TREE_WPC": 0, "SWDFT_TREE_WV": 2}),
+    (80, 90, 32, 32, False, 1, {"SWDFT_TREE_WPC": 2, "SWDFT_TREE_WV": 2, "SWDFT_TREE_KG": 1}),
+    (100, 140, 16, 8, True, 1, {"SWDFT_TREE_WPC": 1, "SWDFT_TREE_WV": 2, "SWDFT_TREE_KG": 2}),
+], ids=["c16x16-b3-cap2", "r8x8-cap1-kg1", "r32x8-b2-cap1", "r16x16-nocap-slab16",
+        "c32x8-b2-cap1-wv2", "r16x32-nocap-wv2", "r32x32-kg1-cap2-wv2", "c16x8-kg2-cap1-wv2"])
 def test_tree_resident_cap(swd, orc, N0, N1, n0, n1, cplx, batch, env):
-    """Launches capped at one or two resident waves per CU (padding LDS) and
-    uncapped ones compute the same transform."""
+    """Launches capped at one or two resident workgroups per CU (padding
+    LDS), uncapped ones, and strips shared by two waves compute the same
+    transform."""
     gen = workloads.normal_complex if cplx else workloads.normal_real
     xs = np.stack([gen((N0, N1), seed=N0 + N1 + b) for b in range(batch)])
     dt = torch.complex64 if cplx else torch.float32
@@ -254,7 +260,9 @@ def test_tree_resident_cap(swd, orc, N0, N1, n0, n1, cplx, batch, env):
         return p.describe(), y.cpu().numpy()
 
     desc, y = _with_env(env, run)
-    assert f"waves_per_cu={env['SWDFT_TREE_WPC']}" in desc
+    assert f"groups_per_cu={env['SWDFT_TREE_WPC']}" in desc
+    if "SWDFT_TREE_WV" in env:
+        assert f"waves_per_strip={env['SWDFT_TREE_WV']}" in desc
     for b in range(batch):
         ref = orc.swdft2d(xs[b].astype(np.complex128 if cplx else np.float64), n0, n1)
         assert rel_err(y[b], ref) <= TOL_F32, b
@@ -271,7 +279,7 @@ def test_tree_capped_dispatch_order_sampled(swd, orc):
         return p.describe(), sampled_check(swd, orc, x_np, 16, 16, 2048, 1004)
 
     desc, (got, ref) = _with_env({"SWDFT_TREE_WPC": 1, "SWDFT_TREE_SLAB": 16}, run)
-    assert "waves_per_cu=1" in desc and "order=dispatch" in desc, desc
+    assert "groups_per_cu=1" in desc and "order=dispatch" in desc, desc
     assert rel_err(got, ref) <= TOL_F32
 
 
