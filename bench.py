@@ -36,7 +36,7 @@ METRIC = "SWDFT coeffs/s + % HBM roofline, FP32 tree vs plain FP64 direct @ rel 
 PEAK_HBM_GBS = 8000.0
 # the kernel and the host code that picks its launch shape (tile, occupancy cap)
 KERNEL_SOURCES = ["paper_1707_08213_amd/csrc/tree_fwd_kernel.h",
-                  "paper_1707_08213_amd/csrc/tree_fwd_n16_r.hip",
+                  "paper_1707_08213_amd/csrc/tree_fwd_n16_r_16.hip",
                   "paper_1707_08213_amd/csrc/tree_fwd.hip",
                   "paper_1707_08213_amd/csrc/tree_config.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tree_fwd_sin1024_traffic.json")

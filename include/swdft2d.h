@@ -91,8 +91,8 @@ typedef int swdft_status_t;
 #define SWDFT_E_PLAN 9        /* null or destroyed plan, or wrong plan kind */
 
 #define SWDFT_MAX_WINDOW 32   /* largest n0 or n1 a plan accepts */
-#define SWDFT_MAX_ROW 4194304 /* largest N1 a plan accepts: 64 input rows of it
-                                 (the most one tile stages) stay below 2 GiB,
+#define SWDFT_MAX_ROW 2097152 /* largest N1 a plan accepts: 128 input rows of it
+                                 (the most one tile stages) stay within 2 GiB,
                                  so kernels address them with 32-bit offsets */
 
 typedef struct swdft2d_plan_s* swdft2d_plan_t;

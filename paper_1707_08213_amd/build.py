@@ -8,6 +8,7 @@ from __future__ import annotations
 import concurrent.futures
 import os
 import subprocess
+import time
 import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
@@ -20,7 +21,8 @@ SOURCES = ["abi.hip", "batched_host.hip", "tune.hip", "tree_config.hip", "tree_f
            "dense_mfma_r.hip", "dense_mfma_c.hip", "batched.hip", "batched_tree_r.hip",
            "batched_tree_c.hip", "batched_dense_r.hip", "batched_dense_c.hip"] + [
     f"tree_{kind}_n{n}_{t}.hip" for kind in ("fwd", "adj") for n in (1, 2, 4, 8, 16, 32)
-    for t in ("r", "c")]
+    for t in ("r", "c")] + [
+    f"tree_fwd_n{n0}_{t}_{n1}.hip" for n0 in (16, 32) for t in ("r", "c") for n1 in (16, 32)]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -33,43 +35,62 @@ FLAGS = [
 ]
 
 
-def _newest_header() -> float:
-    newest = 0.0
-    for d in (CSRC, os.path.join(ROOT, "include")):
-        for f in os.listdir(d):
-            if f.endswith(".h"):
-                newest = max(newest, os.path.getmtime(os.path.join(d, f)))
-    return newest
+def _deps(dep_file: str):
+    """Files a translation unit read when it was last compiled (from the
+    compiler's -MMD output), or None when unknown."""
+    try:
+        text = open(dep_file).read()
+    except OSError:
+        return None
+    text = text.replace("\\\n", " ")
+    _, _, rest = text.partition(":")
+    return [f for f in rest.split() if f]
+
+
+def _up_to_date(src_path: str, obj: str) -> bool:
+    if not os.path.exists(obj):
+        return False
+    deps = _deps(obj[:-2] + ".d")
+    if deps is None:
+        return False
+    t = os.path.getmtime(obj)
+    for f in [src_path] + deps:
+        if not os.path.exists(f) or os.path.getmtime(f) >= t:
+            return False
+    return True
 
 
 def _compile(src: str, verbose: bool, incremental: bool = False) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    if incremental and os.path.exists(obj):
-        t = os.path.getmtime(obj)
-        if t > os.path.getmtime(os.path.join(CSRC, src)) and t > _newest_header():
-            return obj
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
-    if verbose:
-        print(" ".join(cmd), flush=True)
+    src_path = os.path.join(CSRC, src)
+    if incremental and _up_to_date(src_path, obj):
+        return obj
+    cmd = [HIPCC, *FLAGS, "-MMD", "-MF", obj[:-2] + ".d", "-c", src_path, "-o", obj]
+    t0 = time.time()
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
-    noisy = [ln for ln in r.stderr.splitlines() if "packed-fp32-ops" not in ln and ln.strip()]
-    if verbose and noisy:
-        print("\n".join(noisy), flush=True)
+    if verbose:
+        print(f"{time.time() - t0:6.1f} s  {src}", flush=True)
+        noisy = [ln for ln in r.stderr.splitlines() if "packed-fp32-ops" not in ln and ln.strip()]
+        if noisy:
+            print("\n".join(noisy), flush=True)
     return obj
 
 
 def build(verbose: bool = False, jobs: int = 8, incremental: bool = False) -> str:
-    """Compile every source (or, with incremental=True, only those older than
-    their source or any header) and link libswdft2d.so."""
+    """Compile every source (or, with incremental=True, only those whose
+    object is older than the source or a header it includes) and link
+    libswdft2d.so."""
     os.makedirs(BUILD, exist_ok=True)
     # the largest window instantiations take longest: start them first
     def cost(src):
         if src.startswith("batched_"):
             return 100
-        return max([int(t[1:]) for t in src[:-4].split("_") if t[:1] == "n" and t[1:].isdigit()]
-                   or [0])
+        parts = src[:-4].split("_")
+        n0 = max([int(t[1:]) for t in parts if t[:1] == "n" and t[1:].isdigit()] or [0])
+        n1 = int(parts[-1]) if parts[-1].isdigit() else 0
+        return n0 * (4 if n1 else 1) + n1
     order = sorted(SOURCES, key=lambda s: -cost(s))
     with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose, incremental), order))

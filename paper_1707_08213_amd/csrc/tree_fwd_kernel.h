@@ -49,6 +49,7 @@
 #include <type_traits>
 
 #include "internal.h"
+#include "swdft2d.h"
 
 namespace swdft {
 namespace tree {
@@ -243,8 +244,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uin
 
 typedef unsigned u2v __attribute__((ext_vector_type(2)));
 
-// A byte offset no buffer of this library reaches (ranges stay below 2 GiB):
-// a load there returns zero, a store there is dropped.
+// A byte offset no buffer of this library reaches: a load there returns zero,
+// a store there is dropped. Input resources span at most 128 rows (TreeCfg::CR)
+// of at most SWDFT_MAX_ROW elements of 8 bytes, i.e. at most 2^31 bytes, and
+// offsets past this value plus one chunk stay below 2^32.
 constexpr uint32_t kOutOfRange = 0x80000000u;
 
 // Input element at byte offset off of a buffer resource; zero past its end.
@@ -293,6 +296,8 @@ struct TreeCfg {
   static constexpr int ZROW = QW * ZS;                      // float2 per chunk row in LDS
   static constexpr int LDS_FLOAT2 = CR * ZROW;
   static_assert(KT == 1 || KT < N0W, "a split stream needs KG * WV < n0");
+  static_assert((int64_t)CR * SWDFT_MAX_ROW * 8 <= (int64_t)kOutOfRange,
+                "one chunk of input rows must stay addressable with 32-bit offsets");
   static_assert(N1W * KG <= 64, "one wave must hold a whole window column");
 };
 

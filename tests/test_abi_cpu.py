@@ -51,6 +51,8 @@ def make_plan(N0, N1, n0, n1, dtype=_lib.SWDFT_R32, batch=1):
     ((128, 128, 64, 4, 0, 1), "SWDFT_E_WINDOW"),
     ((1 << 40, 1 << 40, 32, 32, 0, 1), "SWDFT_E_OVERFLOW"),
     ((1 << 20, 1 << 20, 32, 32, 0, 1 << 20), "SWDFT_E_OVERFLOW"),
+    ((64, 1 << 21, 16, 16, 1, 1), "SWDFT_OK"),            # longest row a plan accepts
+    ((64, (1 << 21) + 1, 16, 16, 1, 1), "SWDFT_E_OVERFLOW"),
 ])
 def test_plan_validation(args, status):
     st, h = make_plan(*args)
@@ -197,6 +199,7 @@ def test_batched_plan_validation():
         ([(64, 64, 8, 8)], _lib.SWDFT_R64, "SWDFT_E_DTYPE"),
         ([(64, 64, 8, 8)], 9, "SWDFT_E_ARG"),
         ([(0, 64, 8, 8)], _lib.SWDFT_R32, "SWDFT_E_ARG"),
+        ([(64, (1 << 21) + 1, 8, 8)], _lib.SWDFT_R32, "SWDFT_E_OVERFLOW"),  # row too long
     ]
     for shapes, dt, name in cases:
         st, h = make_batched(shapes, dt)
