@@ -1,10 +1,12 @@
-"""FP64 oracle for the 2D sliding-window DFT (TEST INFRASTRUCTURE).
+"""FP64 oracle for the 2D sliding-window DFT and its 3D extension (TEST
+INFRASTRUCTURE).
 
 Only ``tests/``, the smoke check and the bench's CPU-baseline leg may import
 this package. The GPU library never does, and the two share no code.
 
 The arithmetic lives in ``oracle.c`` (plain C, FP64, the definition of
-Eq. (2) of Sec. 4.1 evaluated window by window, and its explicit adjoint). This
+Eq. (2) of Sec. 4.1 evaluated window by window, its explicit adjoint, and the
+3D definition that the trees of Sec. 4.8 reach). This
 wrapper only marshals numpy arrays and compiles the C file with gcc when the
 shared object is missing or older than its source.
 """
@@ -61,6 +63,9 @@ class Oracle:
         lib.oracle_swdft2d.restype = ctypes.c_int
         lib.oracle_swdft2d_adjoint.argtypes = [vp, vp, i64, i64, i32, i32, i32, vp, vp, i64, vp, vp]
         lib.oracle_swdft2d_adjoint.restype = ctypes.c_int
+        lib.oracle_swdft3d.argtypes = [vp, vp, i64, i64, i64, i32, i32, i32, i32, vp, vp, vp,
+                                       i64, vp, vp]
+        lib.oracle_swdft3d.restype = ctypes.c_int
         lib.oracle_num_threads.restype = ctypes.c_int
         self.lib = lib
 
@@ -125,6 +130,36 @@ class Oracle:
         return dx.reshape(N0, N1) if pixels is None else dx
 
 
+    def swdft3d(self, x, n0: int, n1: int, n2: int, windows=None, norm: str = "none") -> np.ndarray:
+        """Direct 3D SWDFT of one N0 x N1 x N2 volume (real or complex).
+
+        windows: None for every window -> complex128 [P0, P1, P2, n0, n1, n2];
+                 or (q0, q1, q2) int arrays -> complex128 [len(q0), n0, n1, n2].
+        """
+        x = np.asarray(x)
+        if x.ndim != 3:
+            raise ValueError("oracle.swdft3d takes one 3D volume")
+        N0, N1, N2 = x.shape
+        xr = _as_f64(x.real)
+        xi = _as_f64(x.imag) if np.iscomplexobj(x) else None
+        P0, P1, P2 = N0 - n0 + 1, N1 - n1 + 1, N2 - n2 + 1
+        if windows is None:
+            q0 = q1 = q2 = None
+            nwin = P0 * P1 * P2
+        else:
+            q0, q1, q2 = (np.ascontiguousarray(w, dtype=np.int64) for w in windows)
+            nwin = q0.size
+        yr = np.empty((nwin, n0, n1, n2), np.float64)
+        yi = np.empty((nwin, n0, n1, n2), np.float64)
+        rc = self.lib.oracle_swdft3d(_ptr(xr), _ptr(xi), N0, N1, N2, n0, n1, n2,
+                                     int(norm == "ortho"), _ptr(q0), _ptr(q1), _ptr(q2), nwin,
+                                     _ptr(yr), _ptr(yi))
+        if rc != 0:
+            raise ValueError(f"oracle_swdft3d rejected N=({N0},{N1},{N2}) n=({n0},{n1},{n2})")
+        y = yr + 1j * yi
+        return y.reshape(P0, P1, P2, n0, n1, n2) if windows is None else y
+
+
 def get() -> Oracle:
     """The default (unmutated) oracle, compiled on first use if needed."""
     global _default
@@ -142,3 +177,7 @@ def swdft2d(x, n0, n1, windows=None, norm="none"):
 
 def swdft2d_adjoint(dy, N0, N1, pixels=None, norm="none"):
     return get().swdft2d_adjoint(dy, N0, N1, pixels=pixels, norm=norm)
+
+
+def swdft3d(x, n0, n1, n2, windows=None, norm="none"):
+    return get().swdft3d(x, n0, n1, n2, windows=windows, norm=norm)

@@ -1,5 +1,6 @@
 /*
- * FP64 oracle for the 2D sliding-window DFT (2D SWDFT).
+ * FP64 oracle for the 2D sliding-window DFT (2D SWDFT), and for its 3D
+ * extension (Sec. 4.8).
  *
  * TEST INFRASTRUCTURE. Only the test suite, the smoke check and the bench's
  * CPU-baseline leg may load this code; the product path never does. It shares
@@ -228,6 +229,106 @@ int oracle_swdft2d_adjoint(const double* dy_re, const double* dy_im, int64_t N0,
         dx_im[t] = acc_i * scale;
     }
     free(w0r); free(w0i); free(w1r); free(w1i);
+    return ORACLE_OK;
+}
+
+/*
+ * Forward 3D SWDFT at a list of windows: the k-dimensional extension of
+ * Sec. 4.8 (Eq. (7) and its three-dimensional instances), whose trees end in
+ * the plain 3D DFT of every window:
+ *
+ *   a[q0][q1][q2][k0][k1][k2] = s * sum_{j0<n0} sum_{j1<n1} sum_{j2<n2}
+ *        x[q0+j0][q1+j1][q2+j2] * W0[(j0 k0) mod n0] * W1[(j1 k1) mod n1] * W2[(j2 k2) mod n2]
+ *
+ * with s = 1, or 1/sqrt(n0 n1 n2) (the 3D analogue of the scale of Eq. (2)).
+ *   x_re, x_im : input [N0][N1][N2], row-major; x_im may be NULL (real input).
+ *   q0, q1, q2 : window corners, nwin entries; all NULL for every window in
+ *                row-major (q0, q1, q2) order (nwin = P0*P1*P2).
+ *   y_re, y_im : output [nwin][n0][n1][n2], k2 fastest.
+ * Returns 0, or 1 on a bad argument (nothing written).
+ */
+int oracle_swdft3d(const double* x_re, const double* x_im, int64_t N0, int64_t N1, int64_t N2,
+                   int32_t n0, int32_t n1, int32_t n2, int32_t ortho,
+                   const int64_t* q0, const int64_t* q1, const int64_t* q2, int64_t nwin,
+                   double* y_re, double* y_im)
+{
+    if (check_shape(N0, N1, n0, n1) != ORACLE_OK || N2 < 1 || n2 < 1 || n2 > N2 || !x_re ||
+        !y_re || !y_im || nwin < 0)
+        return ORACLE_EARG;
+    const int64_t P0 = N0 - n0 + 1, P1 = N1 - n1 + 1, P2 = N2 - n2 + 1;
+    const int given = (q0 != NULL) + (q1 != NULL) + (q2 != NULL);
+    if (given != 0 && given != 3) return ORACLE_EARG;
+    if (given == 0 && nwin != P0 * P1 * P2) return ORACLE_EARG;
+    if (given == 3) {
+        for (int64_t w = 0; w < nwin; ++w)
+            if (q0[w] < 0 || q0[w] >= P0 || q1[w] < 0 || q1[w] >= P1 || q2[w] < 0 || q2[w] >= P2)
+                return ORACLE_EARG;
+    }
+
+    double* w0r = (double*)malloc(sizeof(double) * (size_t)n0);
+    double* w0i = (double*)malloc(sizeof(double) * (size_t)n0);
+    double* w1r = (double*)malloc(sizeof(double) * (size_t)n1);
+    double* w1i = (double*)malloc(sizeof(double) * (size_t)n1);
+    double* w2r = (double*)malloc(sizeof(double) * (size_t)n2);
+    double* w2i = (double*)malloc(sizeof(double) * (size_t)n2);
+    if (!w0r || !w0i || !w1r || !w1i || !w2r || !w2i) {
+        free(w0r); free(w0i); free(w1r); free(w1i); free(w2r); free(w2i);
+        return ORACLE_EARG;
+    }
+    make_twiddles(n0, w0r, w0i);
+    make_twiddles(n1, w1r, w1i);
+    make_twiddles(n2, w2r, w2i);
+#if ORACLE_MUTATION == 10
+    if (n1 <= n2) make_twiddles(n1, w2r, w2i); /* mutation: axis-2 roots of length n1 */
+#endif
+    const double scale = ortho ? 1.0 / sqrt((double)n0 * (double)n1 * (double)n2) : 1.0;
+    int64_t j2_end = n2;
+#if ORACLE_MUTATION == 8
+    j2_end = n2 - 1; /* mutation: last slice of every window dropped */
+#endif
+    const int64_t nk = (int64_t)n0 * n1 * n2;
+
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t w = 0; w < nwin; ++w) {
+        const int64_t a0 = q0 ? q0[w] : w / (P1 * P2);
+        const int64_t a1 = q1 ? q1[w] : (w / P2) % P1;
+        const int64_t a2 = q2 ? q2[w] : w % P2;
+        double* yr = y_re + w * nk;
+        double* yi = y_im + w * nk;
+        for (int k0 = 0; k0 < n0; ++k0) {
+            for (int k1 = 0; k1 < n1; ++k1) {
+                for (int k2 = 0; k2 < n2; ++k2) {
+                    double acc_r = 0.0, acc_i = 0.0;
+                    for (int j0 = 0; j0 < n0; ++j0) {
+                        for (int j1 = 0; j1 < n1; ++j1) {
+                            for (int64_t j2 = 0; j2 < j2_end; ++j2) {
+                                const int64_t idx = ((a0 + j0) * N1 + (a1 + j1)) * N2 + (a2 + j2);
+                                const double xr = x_re[idx];
+                                const double xi = x_im ? x_im[idx] : 0.0;
+                                const int e0 = (int)(((int64_t)j0 * k0) % n0);
+                                int e1 = (int)(((int64_t)j1 * k1) % n1);
+                                int e2 = (int)((j2 * k2) % n2);
+#if ORACLE_MUTATION == 9
+                                e1 = (int)(((int64_t)j1 * k2) % n1); /* mutation: k1 and k2 swapped */
+                                e2 = (int)((j2 * k1) % n2);
+#endif
+                                /* t = W0[e0] * W1[e1] * W2[e2] */
+                                const double ur = w0r[e0] * w1r[e1] - w0i[e0] * w1i[e1];
+                                const double ui = w0r[e0] * w1i[e1] + w0i[e0] * w1r[e1];
+                                const double tr = ur * w2r[e2] - ui * w2i[e2];
+                                const double ti = ur * w2i[e2] + ui * w2r[e2];
+                                acc_r += xr * tr - xi * ti;
+                                acc_i += xr * ti + xi * tr;
+                            }
+                        }
+                    }
+                    yr[((int64_t)k0 * n1 + k1) * n2 + k2] = acc_r * scale;
+                    yi[((int64_t)k0 * n1 + k1) * n2 + k2] = acc_i * scale;
+                }
+            }
+        }
+    }
+    free(w0r); free(w0i); free(w1r); free(w1i); free(w2r); free(w2i);
     return ORACLE_OK;
 }
 

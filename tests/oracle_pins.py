@@ -10,7 +10,10 @@ disagrees with:
   * invariants (Parseval per window, the shift theorem between neighbouring
     windows that recursive sliding DFTs are built on (Sec. 2), linearity),
   * the adjoint identities (dot-product test, exact central differences of a
-    quadratic loss).
+    quadratic loss),
+  * for the 3D extension (Sec. 4.8): numpy.fft.fftn per window, separable
+    inputs against 1D sliding DFTs, exact Gaussian integers, the sliding
+    recurrence along the last axis, Parseval and the orthonormal scale.
 
 ``ALL_PINS`` lists them so the mutation test can run every pin against
 deliberately broken builds of the oracle.
@@ -281,7 +284,106 @@ def pin_quadratic_fd(orc):
         assert abs(fd - grad[r, c]) < 1e-10 * max(1.0, abs(fd)), (r, c, fd, grad[r, c])
 
 
+# ---- 3D SWDFT (the k-dimensional extension of Sec. 4.8, k = 3)
+
+def pin3d_fftn(orc):
+    """Each 3D window equals numpy.fft.fftn of that window (real and complex
+    x; unequal window sides so axes cannot be confused; whole-array window)."""
+    rng = np.random.default_rng(31)
+    for (N, n) in [((7, 9, 11), (2, 4, 8)), ((9, 8, 6), (8, 1, 4)), ((5, 6, 7), (1, 4, 2)),
+                   ((6, 7, 8), (4, 4, 4)), ((4, 8, 2), (4, 8, 2))]:
+        for cplx in (False, True):
+            x = rng.standard_normal(N)
+            if cplx:
+                x = x + 1j * rng.standard_normal(N)
+            y = orc.swdft3d(x, *n)
+            win = np.lib.stride_tricks.sliding_window_view(x, n)
+            ref = np.fft.fftn(win, axes=(-3, -2, -1))
+            assert y.shape == tuple(N[i] - n[i] + 1 for i in range(3)) + tuple(n)
+            assert _rel(y, ref) < 1e-13, (N, n, cplx)
+
+
+def pin3d_separable(orc):
+    """x = a (x) b (x) c (outer product): every window's 3D DFT is the
+    product of the three 1D sliding DFTs, each taken from numpy.fft.fft."""
+    rng = np.random.default_rng(32)
+    (N0, N1, N2), (n0, n1, n2) = (10, 9, 12), (4, 2, 8)
+    a = rng.standard_normal(N0) + 1j * rng.standard_normal(N0)
+    b = rng.standard_normal(N1)
+    c = rng.standard_normal(N2) + 1j * rng.standard_normal(N2)
+    x = a[:, None, None] * b[None, :, None] * c[None, None, :]
+    y = orc.swdft3d(x, n0, n1, n2)
+    A = np.fft.fft(np.lib.stride_tricks.sliding_window_view(a, n0), axis=-1)
+    B = np.fft.fft(np.lib.stride_tricks.sliding_window_view(b, n1), axis=-1)
+    C = np.fft.fft(np.lib.stride_tricks.sliding_window_view(c, n2), axis=-1)
+    ref = (A[:, None, None, :, None, None] * B[None, :, None, None, :, None] *
+           C[None, None, :, None, None, :])
+    assert _rel(y, ref) < 1e-13
+
+
+def pin3d_exact_small(orc):
+    """Gaussian-integer brute force, exact, with n_i <= 4 (all twiddles are
+    powers of -i, so integer inputs give integer outputs bit for bit)."""
+    rng = np.random.default_rng(33)
+    for (N, n) in [((3, 4, 5), (2, 4, 2)), ((4, 3, 4), (4, 1, 4))]:
+        xr = rng.integers(-9, 10, size=N)
+        xi = rng.integers(-9, 10, size=N)
+        y = orc.swdft3d((xr + 1j * xi).astype(np.complex128), *n)
+        P = [N[i] - n[i] + 1 for i in range(3)]
+        for q in np.ndindex(*P):
+            for k in np.ndindex(*n):
+                acc_r = acc_i = 0
+                for j in np.ndindex(*n):
+                    e = sum((4 // n[i]) * j[i] * k[i] if n[i] > 1 else 0 for i in range(3))
+                    a = int(xr[q[0] + j[0], q[1] + j[1], q[2] + j[2]])
+                    b = int(xi[q[0] + j[0], q[1] + j[1], q[2] + j[2]])
+                    for _ in range(e % 4):  # multiply by -i
+                        a, b = b, -a
+                    acc_r += a
+                    acc_i += b
+                got = y[q + k]
+                assert got.real == acc_r and got.imag == acc_i, (N, n, q, k)
+
+
+def pin3d_shift_axis2(orc):
+    """Sliding one step along the last axis replaces the plane j2 = 0 by the
+    plane j2 = n2 and rotates by W2^{-k2}:
+        a[q0][q1][q2+1][k] = W2^{-k2} (a[q0][q1][q2][k] + F01(x[.., q2+n2] - x[.., q2])[k0][k1])
+    where F01 is the 2D DFT over the first two axes (numpy.fft.fft2)."""
+    rng = np.random.default_rng(34)
+    (N0, N1, N2), (n0, n1, n2) = (7, 8, 12), (4, 2, 8)
+    x = rng.standard_normal((N0, N1, N2)) + 1j * rng.standard_normal((N0, N1, N2))
+    y = orc.swdft3d(x, n0, n1, n2)
+    rot = np.exp(2j * np.pi * np.arange(n2) / n2)[None, None, :]
+    for q0 in range(N0 - n0 + 1):
+        for q1 in range(N1 - n1 + 1):
+            for q2 in range(N2 - n2):
+                d = np.fft.fft2(x[q0:q0 + n0, q1:q1 + n1, q2 + n2] - x[q0:q0 + n0, q1:q1 + n1, q2])
+                pred = rot * (y[q0, q1, q2] + d[:, :, None])
+                assert np.max(np.abs(y[q0, q1, q2 + 1] - pred)) < 1e-11
+
+
+def pin3d_parseval_ortho(orc):
+    """Per window: sum_k |a_k|^2 = n0 n1 n2 sum_j |x_j|^2; the orthonormal
+    scale 1/sqrt(n0 n1 n2) makes the two sides equal; sampled windows equal
+    the same entries of the full output."""
+    rng = np.random.default_rng(35)
+    (N0, N1, N2), (n0, n1, n2) = (9, 10, 11), (4, 8, 2)
+    x = rng.standard_normal((N0, N1, N2))
+    win = np.lib.stride_tricks.sliding_window_view(x, (n0, n1, n2))
+    energy = np.sum(np.abs(win) ** 2, axis=(-3, -2, -1))
+    y = orc.swdft3d(x, n0, n1, n2)
+    assert np.allclose(np.sum(np.abs(y) ** 2, axis=(-3, -2, -1)), n0 * n1 * n2 * energy, rtol=1e-12)
+    yo = orc.swdft3d(x, n0, n1, n2, norm="ortho")
+    assert np.allclose(np.sum(np.abs(yo) ** 2, axis=(-3, -2, -1)), energy, rtol=1e-12)
+    q = (np.array([0, 5, 2, 5]), np.array([0, 2, 1, 2]), np.array([9, 0, 4, 9]))
+    assert np.array_equal(orc.swdft3d(x, n0, n1, n2, windows=q), y[q])
+
+
+PINS_3D = [pin3d_fftn, pin3d_separable, pin3d_exact_small, pin3d_shift_axis2,
+           pin3d_parseval_ortho]
+
 ALL_PINS = [pin_matrix_form, pin_fft2, pin_whole_array, pin_exact_small, pin_impulse,
             pin_constant, pin_onbin_exponential, pin_onbin_cosine, pin_parseval,
             pin_shift_theorem, pin_linearity_and_sampling, pin_adjoint_dot,
-            pin_adjoint_sampled, pin_quadratic_fd]
+            pin_adjoint_sampled, pin_quadratic_fd] + PINS_3D

@@ -23,6 +23,15 @@ def test_oracle_rejects_bad_shapes(orc):
         orc.swdft2d(x, 2, 2, windows=(np.array([3]), np.array([0])))
 
 
+def test_oracle3d_rejects_bad_shapes(orc):
+    x = np.zeros((4, 4, 4))
+    for n in [(5, 1, 1), (1, 5, 1), (1, 1, 5), (0, 2, 2)]:
+        with pytest.raises(ValueError):
+            orc.swdft3d(x, *n)
+    with pytest.raises(ValueError):
+        orc.swdft3d(x, 2, 2, 2, windows=(np.array([0]), np.array([0]), np.array([3])))
+
+
 MUTANTS = {
     1: "inverse twiddle sign",
     2: "last window column dropped",
@@ -31,6 +40,9 @@ MUTANTS = {
     5: "k0 and k1 swapped",
     6: "adjoint without conjugate",
     7: "adjoint window range off by one",
+    8: "3D: last slice of every window dropped",
+    9: "3D: k1 and k2 swapped",
+    10: "3D: axis-2 roots of the wrong length",
 }
 
 
