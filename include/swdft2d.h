@@ -202,6 +202,45 @@ swdft_status_t swdft2d_tune(swdft2d_plan_t plan, const void* x, void* y, hipStre
  * given byte count. */
 swdft_status_t swdft2d_write_probe(void* y, int64_t bytes, hipStream_t stream);
 
+/* ---- 3D sliding-window DFT: the k-dimensional extension of Sec. 4.8 with
+ * k = 3. Its trees run the levels of axis 2, then axis 1, then axis 0 (the
+ * three instances of Eq. (7) printed there) and end in the 3D DFT of every
+ * window:
+ *   y[b][q0][q1][q2][k0][k1][k2] = s * sum_{j<n} x[b][q0+j0][q1+j1][q2+j2]
+ *                                  * W0^(j0 k0) W1^(j1 k1) W2^(j2 k2)
+ * with W_n = exp(-2 pi i / n) and s = 1 (NONE) or 1/sqrt(n0 n1 n2) (ORTHO).
+ * x is [batch][N0][N1][N2] row-major (float for R32, float2 for C32); y is
+ * [batch][P0][P1][P2][n0][n1][n2] complex64, P_i = N_i - n_i + 1, k2 fastest.
+ * The caller owns x and y; y must not overlap x. */
+typedef struct swdft3d_plan_s* swdft3d_plan_t;
+
+/* Checks, in this order: out != NULL (E_ARG); sizes >= 1 and dtype known
+ * (E_ARG); dtype R32 or C32 (E_DTYPE); n_i powers of two (E_NOT_POW2);
+ * n_i <= N_i, n0 in {2, 4, 8, 16} and n1, n2 in {2, 4, 8} (E_WINDOW); element,
+ * byte and tile counts fit (E_OVERFLOW). Builds the twiddle vectors of the
+ * three axes in FP64 and rounds them once to FP32. Touches no GPU. On error
+ * *out is set to NULL. */
+swdft_status_t swdft3d_plan(swdft3d_plan_t* out, int64_t N0, int64_t N1, int64_t N2, int32_t n0,
+                            int32_t n1, int32_t n2, swdft_dtype_t dtype, int64_t batch);
+
+/* Select the output scale; affects later execs. */
+swdft_status_t swdft3d_set_norm(swdft3d_plan_t plan, swdft_norm_t norm);
+
+/* Enqueue the transform on `stream` (no synchronisation). x must be aligned
+ * to its element size and y to 8 bytes (E_ALIGN); null pointers and
+ * overlapping x/y give E_ARG; a failed launch gives E_DEVICE. */
+swdft_status_t swdft3d_exec(swdft3d_plan_t plan, const void* x, void* y, hipStream_t stream);
+
+/* batch*P0*P1*P2*n0*n1*n2, or -1 for a null or destroyed plan. */
+int64_t swdft3d_output_elems(swdft3d_plan_t plan);
+
+/* Launch shape as text (algorithm, tile, slab, counts). */
+swdft_status_t swdft3d_describe(swdft3d_plan_t plan, char* buf, int32_t len);
+
+/* Free the plan (E_PLAN if already destroyed). NULL is accepted. The caller
+ * must not destroy a plan while work it enqueued is in flight. */
+swdft_status_t swdft3d_destroy(swdft3d_plan_t plan);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,8 +20,8 @@ import torch
 from . import _lib
 from ._lib import SwdftError, check, lib
 
-__all__ = ["Plan", "BatchedPlan", "swdft2d", "swdft2d_batched", "swdft2d_backward", "SWDFT2dFn",
-           "write_probe", "SwdftError", "output_shape"]
+__all__ = ["Plan", "BatchedPlan", "Plan3D", "swdft2d", "swdft2d_batched", "swdft2d_backward",
+           "swdft3d", "SWDFT2dFn", "write_probe", "SwdftError", "output_shape"]
 
 _DTYPES = {
     torch.float32: _lib.SWDFT_R32, torch.complex64: _lib.SWDFT_C32,
@@ -273,6 +273,83 @@ def swdft2d(x: torch.Tensor, n0: int, n1: int, norm: str = "none", algo: str = "
     xb, squeeze = _batched(x.contiguous())
     B, N0, N1 = xb.shape
     y = _cached_plan(N0, N1, n0, n1, xb.dtype, B, norm, algo).forward(xb)
+    return y[0] if squeeze else y
+
+
+class Plan3D:
+    """One swdft3d plan: `batch` volumes of N0 x N1 x N2, n0 x n1 x n2 windows
+    (the 3D extension of Sec. 4.8)."""
+
+    def __init__(self, N0, N1, N2, n0, n1, n2, dtype=torch.float32, batch=1, norm="none"):
+        if dtype not in (torch.float32, torch.complex64):
+            raise TypeError(f"3D plans take float32 or complex64 input, got {dtype}")
+        self.N = (int(N0), int(N1), int(N2))
+        self.n = (int(n0), int(n1), int(n2))
+        self.batch, self.dtype = int(batch), dtype
+        h = ctypes.c_void_p()
+        check(lib.swdft3d_plan(ctypes.byref(h), *self.N, *self.n, _DTYPES[dtype], self.batch),
+              "swdft3d_plan")
+        self.handle = h
+        try:
+            check(lib.swdft3d_set_norm(h, _NORMS[norm]), "swdft3d_set_norm")
+        except Exception:
+            lib.swdft3d_destroy(h)
+            self.handle = None
+            raise
+        self.norm = norm
+
+    @property
+    def out_shape(self):
+        P = tuple(self.N[i] - self.n[i] + 1 for i in range(3))
+        return (self.batch,) + P + self.n
+
+    def output_elems(self) -> int:
+        return int(lib.swdft3d_output_elems(self.handle))
+
+    def describe(self) -> str:
+        buf = ctypes.create_string_buffer(512)
+        check(lib.swdft3d_describe(self.handle, buf, 512), "swdft3d_describe")
+        return buf.value.decode()
+
+    def exec_ptr(self, x_ptr: int, y_ptr: int, stream: int = 0) -> None:
+        check(lib.swdft3d_exec(self.handle, x_ptr, y_ptr, stream), "swdft3d_exec")
+
+    def forward(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        want = (self.batch,) + self.N
+        if x.dtype != self.dtype or not x.is_cuda or not x.is_contiguous() or \
+                tuple(x.shape) != want:
+            raise ValueError(f"x must be a contiguous cuda {self.dtype} tensor of shape {want}, "
+                             f"got {x.dtype} {tuple(x.shape)} on {x.device}")
+        if out is None:
+            out = torch.empty(self.out_shape, dtype=torch.complex64, device=x.device)
+        elif (out.dtype != torch.complex64 or tuple(out.shape) != self.out_shape
+              or not out.is_contiguous() or out.device != x.device):
+            raise ValueError("out has the wrong shape, dtype or device")
+        with torch.cuda.device(x.device):
+            stream = torch.cuda.current_stream(x.device).cuda_stream
+            self.exec_ptr(x.data_ptr(), out.data_ptr(), stream)
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            check(lib.swdft3d_destroy(self.handle), "swdft3d_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def swdft3d(x: torch.Tensor, n0: int, n1: int, n2: int, norm: str = "none") -> torch.Tensor:
+    """3D sliding-window DFT of every n0 x n1 x n2 window of x ([N0,N1,N2] or
+    [B,N0,N1,N2]) -> complex64 [B,P0,P1,P2,n0,n1,n2]."""
+    x = x.contiguous()
+    squeeze = x.dim() == 3
+    xb = x.unsqueeze(0) if squeeze else x
+    B, N0, N1, N2 = xb.shape
+    y = Plan3D(N0, N1, N2, n0, n1, n2, dtype=xb.dtype, batch=B, norm=norm).forward(xb)
     return y[0] if squeeze else y
 
 

@@ -18,6 +18,13 @@ struct TwiddlesF32 {
   float2 w1[kMaxWindow];
 };
 
+// Twiddle vectors of the three axes of a 3D plan.
+struct Twiddles3F32 {
+  float2 w0[kMaxWindow];
+  float2 w1[kMaxWindow];
+  float2 w2[kMaxWindow];
+};
+
 struct TwiddlesF64 {
   double2 w0[kMaxWindow];
   double2 w1[kMaxWindow];
@@ -39,6 +46,23 @@ struct TreeGeom {
   int32_t lds_cu;          // LDS bytes per CU (used to impose the cap)
   int32_t order;           // tile order: 0 = a contiguous range per XCD, 1 = dispatch order
   int32_t wv;              // waves per workgroup sharing one strip, 1 or 2
+};
+
+// Geometry of one 3D forward launch. One wave owns a strip of window
+// columns along axis 2 at one window row q1 of axis 1, and a slab of S window
+// rows along axis 0.
+struct Tree3Geom {
+  int64_t N0, N1, N2, P0, P1, P2;
+  int64_t x_image_stride;  // elements between volumes of x
+  int64_t y_image_stride;  // float2 between volumes of y
+  int32_t S;               // output rows (axis 0) per wave
+  int32_t nstrips;         // ceil(P2 / window columns per wave)
+  int32_t nslabs;          // ceil(P0 / S)
+  int32_t batch;
+  float scale;             // 1 or 1/sqrt(n0 n1 n2)
+  int32_t wpc;             // resident workgroups per CU: 0 = as many as fit, else capped
+  int32_t lds_cu;          // LDS bytes per CU (used to impose the cap)
+  int32_t order;           // tile order: 0 = a contiguous range per XCD, 1 = dispatch order
 };
 
 // Geometry of one adjoint launch. One wave owns a strip of window columns and
@@ -90,6 +114,13 @@ int tree_fwd_default_kg(int n0, int n1);
 bool tree_fwd_kg_supported(int n0, int n1, int kg);
 bool tree_fwd_wv_supported(int n0, int kg, int wv);
 int tree_fwd_resident_waves(int wpc, int ncu);
+
+// 3D forward tree (tree3d_fwd.hip)
+bool tree3_shape_supported(int n0, int n1, int n2);
+int tree3_columns_per_wave(int n1, int n2);
+int tree3_rows_per_chunk(int n0, int n1, int n2);
+hipError_t launch_tree3_fwd(int n0, int n1, int n2, bool real_input, const void* x, float2* y,
+                            const Tree3Geom& g, const Twiddles3F32& tw, hipStream_t stream);
 
 hipError_t launch_tree_adj(int n0, int n1, bool real_input, const float2* dy, void* ws, void* dx,
                            const AdjGeom& g, const TwiddlesF32& tw, hipStream_t stream);

@@ -12,7 +12,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 _lib = pytest.importorskip("paper_1707_08213_amd._lib",
-                           reason="libswdft2d.so not built (python -m paper_1707_08213_amd.build)")
+                           reason="libswdft2d.so not built (python paper_1707_08213_amd/build.py)")
 lib = _lib.lib
 S = _lib.STATUS_CODE
 
@@ -20,12 +20,13 @@ S = _lib.STATUS_CODE
 def header_functions():
     text = open(os.path.join(ROOT, "include", "swdft2d.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(swdft2d_\w+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(swdft[23]d_\w+)\s*\(", text)))
 
 
 def test_every_declared_symbol_is_exported():
     names = header_functions()
     assert "swdft2d_plan" in names and "swdft2d_exec" in names and "swdft2d_backward" in names
+    assert "swdft3d_plan" in names and "swdft3d_exec" in names
     for name in names:
         assert hasattr(lib, name), f"{name} declared in include/swdft2d.h but not exported"
         assert name in _lib.SIGNATURES, f"{name} has no ctypes signature in the binding"
@@ -213,3 +214,48 @@ def test_batched_plan_validation():
     st, h = make_batched([(64, 64, 8, 8), (64, 64, 8, 8)], offsets=[(0, 0), (0, 57 * 57 * 64)])
     assert st == 0  # shared input, disjoint outputs
     lib.swdft2d_destroy(h)
+
+
+def make_plan3(N, n, dtype=_lib.SWDFT_R32, batch=1):
+    h = ctypes.c_void_p()
+    st = lib.swdft3d_plan(ctypes.byref(h), *N, *n, dtype, batch)
+    return st, h
+
+
+@pytest.mark.parametrize("N,n,dtype,batch,status", [
+    ((16, 16, 16), (8, 8, 8), _lib.SWDFT_R32, 1, "SWDFT_OK"),
+    ((20, 9, 30), (16, 2, 4), _lib.SWDFT_C32, 3, "SWDFT_OK"),
+    ((16, 16, 16), (8, 8, 8), _lib.SWDFT_R64, 1, "SWDFT_E_DTYPE"),
+    ((16, 16, 16), (8, 8, 8), 7, 1, "SWDFT_E_ARG"),
+    ((16, 0, 16), (8, 8, 8), _lib.SWDFT_R32, 1, "SWDFT_E_ARG"),
+    ((16, 16, 16), (8, 8, 8), _lib.SWDFT_R32, 0, "SWDFT_E_ARG"),
+    ((16, 16, 16), (8, 6, 8), _lib.SWDFT_R32, 1, "SWDFT_E_NOT_POW2"),
+    ((16, 4, 16), (8, 8, 8), _lib.SWDFT_R32, 1, "SWDFT_E_WINDOW"),       # n1 > N1
+    ((16, 16, 16), (32, 2, 2), _lib.SWDFT_R32, 1, "SWDFT_E_WINDOW"),     # n0 > N0
+    ((64, 64, 64), (32, 2, 2), _lib.SWDFT_R32, 1, "SWDFT_E_WINDOW"),     # n0 outside {2..16}
+    ((64, 64, 64), (4, 16, 2), _lib.SWDFT_R32, 1, "SWDFT_E_WINDOW"),     # n1 outside {2,4,8}
+    ((64, 64, 64), (4, 2, 1), _lib.SWDFT_R32, 1, "SWDFT_E_WINDOW"),      # n2 outside {2,4,8}
+    ((1 << 30, 1 << 30, 1 << 30), (8, 8, 8), _lib.SWDFT_R32, 1, "SWDFT_E_OVERFLOW"),
+    ((1 << 16, 1 << 16, 40), (2, 2, 2), _lib.SWDFT_R32, 1, "SWDFT_E_OVERFLOW"),  # > 2^31 tiles
+])
+def test_plan3d_validation(N, n, dtype, batch, status):
+    st, h = make_plan3(N, n, dtype, batch)
+    assert _lib.STATUS[st] == status, lib.swdft2d_last_error()
+    if st == 0:
+        P = [N[i] - n[i] + 1 for i in range(3)]
+        assert lib.swdft3d_output_elems(h) == batch * P[0] * P[1] * P[2] * n[0] * n[1] * n[2]
+        buf = ctypes.create_string_buffer(512)
+        assert lib.swdft3d_describe(h, buf, 512) == 0 and b"algo=tree3d" in buf.value
+        assert lib.swdft3d_set_norm(h, 1) == 0
+        assert lib.swdft3d_set_norm(h, 5) == S["SWDFT_E_ARG"]
+        # argument checks before any launch
+        assert lib.swdft3d_exec(h, None, 0x10000, None) == S["SWDFT_E_ARG"]
+        assert lib.swdft3d_exec(h, 0x10002, 0x90000000, None) == S["SWDFT_E_ALIGN"]
+        assert lib.swdft3d_exec(h, 0x10000, 0x90000004, None) == S["SWDFT_E_ALIGN"]
+        assert lib.swdft3d_exec(h, 0x10000, 0x10000 + 64, None) == S["SWDFT_E_ARG"]  # overlap
+        assert lib.swdft3d_destroy(h) == 0
+        assert lib.swdft3d_destroy(h) == S["SWDFT_E_PLAN"]
+        assert lib.swdft3d_output_elems(h) == -1
+    else:
+        assert h.value is None
+    assert lib.swdft3d_plan(None, 8, 8, 8, 2, 2, 2, 0, 1) == S["SWDFT_E_ARG"]

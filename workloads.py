@@ -24,7 +24,8 @@ from __future__ import annotations
 
 import numpy as np
 
-WORKLOAD_SEEDS = {"small64": 1, "sin1024": 2, "cplx2048": 3, "uneven64": 4, "grad256": 5}
+WORKLOAD_SEEDS = {"small64": 1, "sin1024": 2, "cplx2048": 3, "uneven64": 4, "grad256": 5,
+                  "vol128": 6}
 
 UNEVEN_SIDES = (128, 256, 512, 1024)
 UNEVEN_WINDOWS = ((8, 8), (16, 16), (32, 32), (8, 32))
@@ -95,6 +96,26 @@ def window_sample(P0: int, P1: int, count: int, seed: int):
     return flat // P1, flat % P1
 
 
+def window_sample3(P, count: int, seed: int):
+    """Seeded sample of 3D window positions (q0, q1, q2) in [0, P_i), always
+    holding the eight corners and the centre. Returns three int64 arrays."""
+    P0, P1, P2 = (int(v) for v in P)
+    fixed = {(a, b, c) for a in (0, P0 - 1) for b in (0, P1 - 1) for c in (0, P2 - 1)}
+    fixed.add((P0 // 2, P1 // 2, P2 // 2))
+    total = P0 * P1 * P2
+    count = min(count, total)
+    chosen = {(a * P1 + b) * P2 + c for a, b, c in fixed}
+    rng = rng_for(seed)
+    if count > len(chosen):
+        extra = rng.choice(total, size=min(total, count + len(chosen)), replace=False)
+        for e in extra:
+            if len(chosen) >= count:
+                break
+            chosen.add(int(e))
+    flat = np.array(sorted(chosen), dtype=np.int64)
+    return flat // (P1 * P2), (flat // P2) % P1, flat % P2
+
+
 def pixel_sample(N0: int, N1: int, count: int, seed: int):
     """Seeded sample of input pixels (r, c), always holding corners and edges."""
     return window_sample(N0, N1, count, seed)
@@ -139,6 +160,12 @@ def uneven64(seed: int = WORKLOAD_SEEDS["uneven64"], count: int = 64,
     for (N0, N1, n0, n1) in shapes:
         images.append(dict(x=rng.standard_normal((N0, N1)).astype(np.float32), n0=n0, n1=n1))
     return images
+
+
+def vol128(seed: int = WORKLOAD_SEEDS["vol128"], N: int = 128, n: int = 8):
+    """One N x N x N real FP32 volume, N(0,1), with n x n x n windows (the 3D
+    extension of Sec. 4.8): 121^3 windows of 512 coefficients at the defaults."""
+    return dict(x=normal_real((N, N, N), seed), n=(n, n, n))
 
 
 def grad256(seed: int = WORKLOAD_SEEDS["grad256"], batch: int = 16, N: int = 256,
