@@ -344,6 +344,65 @@ def run_cplx2048(args, swd, dev) -> dict:
     return out
 
 
+def oracle_rate3(orc, x3d, n, P, seconds: float, seed: int):
+    """Time the 3D oracle on a seeded window sample sized to about `seconds`."""
+    import workloads
+    q = workloads.window_sample3(P, 64, seed)
+    t0 = time.perf_counter()
+    orc.swdft3d(x3d, *n, windows=q)
+    per_win = (time.perf_counter() - t0) / q[0].size
+    total = P[0] * P[1] * P[2]
+    nwin = int(min(total, max(256, seconds / per_win)))
+    s = workloads.window_sample3(P, nwin, seed + 1)
+    t0 = time.perf_counter()
+    orc.swdft3d(x3d, *n, windows=s)
+    dt = time.perf_counter() - t0
+    nk = n[0] * n[1] * n[2]
+    return {"value": s[0].size * nk / dt, "unit": "coeffs/s", "cores": orc.num_threads(),
+            "kind": "oracle",
+            "sample": f"{s[0].size} of the {P[0]}x{P[1]}x{P[2]} windows (seeded, corners "
+                      f"included), {s[0].size * nk} coefficients in {dt:.1f} s"}
+
+
+def run_vol128(args, swd, dev) -> dict:
+    import numpy as np
+    import torch
+
+    import workloads
+    wl = workloads.vol128()
+    x_np, n = wl["x"], wl["n"]
+    N = x_np.shape
+    P = tuple(N[i] - n[i] + 1 for i in range(3))
+    x = torch.from_numpy(x_np).to(dev).unsqueeze(0)
+    plan = swd.Plan3D(*N, *n)
+    coeffs = plan.output_elems()
+    alg_bytes = coeffs * 8 + x.numel() * 4
+    stream = torch.cuda.current_stream(dev)
+    log(plan.describe())
+    y, avg_ms, step_s = forward_leg(plan, x, args, stream)
+    rf = roofline(alg_bytes, avg_ms, "tree3_fwd_kernel<8,8,8,real>")
+    log(f"tree3d: {avg_ms * 1e3:.1f} us/launch, {rf['achieved']:.0f} GB/s")
+    q = workloads.window_sample3(P, 256, 3006)
+    got = y[0][tuple(torch.from_numpy(a).to(dev) for a in q)].cpu().numpy()
+    probe_ms, _, _ = time_launches(lambda: swd.write_probe(y), max(3, args.steps // 10), stream)
+    probe = {"GB/s": coeffs * 8 / (probe_ms * 1e-3) / 1e9, "bytes": coeffs * 8}
+    probe["frac"] = probe["GB/s"] / PEAK_HBM_GBS
+    del y
+    cpu, err = None, None
+    if not args.no_cpu_baseline:
+        import oracle
+        orc = oracle.get()
+        xd = x_np.astype(np.float64)
+        err = rel(got, orc.swdft3d(xd, *n, windows=q))
+        cpu = oracle_rate3(orc, xd, n, P, args.cpu_seconds, 3007)
+    out = base_record(args, coeffs / step_s, step_s * 1e3, "f32", {
+        "workload": "vol128: one 128x128x128 real FP32 volume, N(0,1), 8x8x8 windows (3D "
+                    "extension) -> 121x121x121x512 complex64 coefficients",
+        "N": list(N), "n": list(n), "batch": 1, "algo": "tree3d", "coeffs_per_step": coeffs})
+    out.update({"roofline": rf, "rel_err": err, "write_probe": probe, "cpu_baseline": cpu})
+    return out
+
+
 def run_grad256(args, swd, dev) -> dict:
     import numpy as np
     import torch
@@ -458,6 +517,7 @@ def run_uneven64(args, swd, dev) -> dict:
 
 
 WORKLOADS = {"sin1024": run_sin1024, "cplx2048": run_cplx2048, "grad256": run_grad256,
+             "vol128": run_vol128,
              "uneven64": run_uneven64}
 
 

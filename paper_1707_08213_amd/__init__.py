@@ -303,6 +303,10 @@ class Plan3D:
         P = tuple(self.N[i] - self.n[i] + 1 for i in range(3))
         return (self.batch,) + P + self.n
 
+    @property
+    def out_dtype(self):
+        return torch.complex64
+
     def output_elems(self) -> int:
         return int(lib.swdft3d_output_elems(self.handle))
 
