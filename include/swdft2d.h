@@ -202,6 +202,52 @@ swdft_status_t swdft2d_tune(swdft2d_plan_t plan, const void* x, void* y, hipStre
  * given byte count. */
 swdft_status_t swdft2d_write_probe(void* y, int64_t bytes, hipStream_t stream);
 
+/* ---- Streaming 2D sliding-window DFT: the order of Sec. 4.3 in which the
+ * loops over trees are innermost, for rows that arrive one after another
+ * (a real-time task). The column-level state of the trees (m0 n0 / 2 complex
+ * values per (window column, k1) stream, m0 = log2 n0) stays resident on the
+ * device between
+ * calls; each call carries any number of new rows and emits every window row
+ * they complete: with R rows after B rows, the window rows q0 in
+ * [max(0, B - n0 + 1), max(0, B + R - n0 + 1)). The emitted values equal
+ * those of swdft2d_exec on the concatenated rows. */
+typedef struct swdft2d_stream_s* swdft2d_stream_t;
+
+/* Checks: out != NULL, N1, n0, n1 >= 1 and dtype known (E_ARG); dtype R32 or
+ * C32 (E_DTYPE); n0, n1 powers of two (E_NOT_POW2); n1 <= N1 and
+ * n_i <= SWDFT_MAX_WINDOW (E_WINDOW); N1 <= SWDFT_MAX_ROW (E_OVERFLOW).
+ * Touches no GPU. The device state, 8 * max(m0 n0 / 2, 1) * 64 bytes per strip
+ * of 64/n1 window columns (about 4 m0 n0 n1 (N1 - n1 + 1) bytes), is
+ * allocated with hipMalloc at the first push, on the current device, and
+ * cleared there with a kernel. */
+swdft_status_t swdft2d_stream_create(swdft2d_stream_t* out, int64_t N1, int32_t n0, int32_t n1,
+                                     swdft_dtype_t dtype);
+
+/* Select the output scale; affects later pushes. */
+swdft_status_t swdft2d_stream_set_norm(swdft2d_stream_t s, swdft_norm_t norm);
+
+/* Rows received so far (-1 for a null or destroyed stream). */
+int64_t swdft2d_stream_rows(swdft2d_stream_t s);
+
+/* Window rows that a push of `rows` rows would emit now (-1 on bad input). */
+int64_t swdft2d_stream_completes(swdft2d_stream_t s, int64_t rows);
+
+/* Append `rows` rows x[rows][N1] (device memory, float or float2) and enqueue
+ * on `stream` the kernel that writes the window rows they complete to
+ * y[count][P1][n0][n1] (complex64, count = swdft2d_stream_completes(s, rows)
+ * before the call; y may be NULL when count is 0). Pushes of one stream must
+ * execute in order (one HIP stream, or synchronised) and on the device that
+ * holds the state (E_ARG otherwise). rows = 0 is a no-op. */
+swdft_status_t swdft2d_stream_push(swdft2d_stream_t s, const void* x, int64_t rows, void* y,
+                                   hipStream_t stream);
+
+/* Start over with no rows: clears the state with a kernel on `stream`. */
+swdft_status_t swdft2d_stream_reset(swdft2d_stream_t s, hipStream_t stream);
+
+/* Free the stream and its device state (E_PLAN if already destroyed; NULL is
+ * accepted). The caller must not destroy it while its work is in flight. */
+swdft_status_t swdft2d_stream_destroy(swdft2d_stream_t s);
+
 /* ---- 3D sliding-window DFT: the k-dimensional extension of Sec. 4.8 with
  * k = 3. Its trees run the levels of axis 2, then axis 1, then axis 0 (the
  * three instances of Eq. (7) printed there) and end in the 3D DFT of every

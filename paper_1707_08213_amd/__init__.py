@@ -20,8 +20,8 @@ import torch
 from . import _lib
 from ._lib import SwdftError, check, lib
 
-__all__ = ["Plan", "BatchedPlan", "Plan3D", "swdft2d", "swdft2d_batched", "swdft2d_backward",
-           "swdft3d", "SWDFT2dFn", "write_probe", "SwdftError", "output_shape"]
+__all__ = ["Plan", "BatchedPlan", "Plan3D", "Stream2D", "swdft2d", "swdft2d_batched",
+           "swdft2d_backward", "swdft3d", "SWDFT2dFn", "write_probe", "SwdftError", "output_shape"]
 
 _DTYPES = {
     torch.float32: _lib.SWDFT_R32, torch.complex64: _lib.SWDFT_C32,
@@ -337,6 +337,60 @@ class Plan3D:
     def close(self):
         if getattr(self, "handle", None) is not None:
             check(lib.swdft3d_destroy(self.handle), "swdft3d_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Stream2D:
+    """Streaming 2D SWDFT over rows of length N1 (the real-time order of
+    Sec. 4.3): push(rows) returns the window rows those rows complete."""
+
+    def __init__(self, N1, n0, n1, dtype=torch.float32, norm="none"):
+        if dtype not in (torch.float32, torch.complex64):
+            raise TypeError(f"streams take float32 or complex64 input, got {dtype}")
+        self.N1, self.n0, self.n1, self.dtype = int(N1), int(n0), int(n1), dtype
+        h = ctypes.c_void_p()
+        check(lib.swdft2d_stream_create(ctypes.byref(h), self.N1, self.n0, self.n1, _DTYPES[dtype]),
+              "swdft2d_stream_create")
+        self.handle = h
+        try:
+            check(lib.swdft2d_stream_set_norm(h, _NORMS[norm]), "swdft2d_stream_set_norm")
+        except Exception:
+            lib.swdft2d_stream_destroy(h)
+            self.handle = None
+            raise
+
+    @property
+    def rows(self) -> int:
+        return int(lib.swdft2d_stream_rows(self.handle))
+
+    def push(self, x: torch.Tensor) -> torch.Tensor:
+        """x: contiguous cuda [R, N1] rows -> complex64 [count, P1, n0, n1]."""
+        if x.dtype != self.dtype or not x.is_cuda or not x.is_contiguous() or \
+                x.dim() != 2 or x.shape[1] != self.N1:
+            raise ValueError(f"x must be a contiguous cuda {self.dtype} tensor [R, {self.N1}]")
+        count = int(lib.swdft2d_stream_completes(self.handle, x.shape[0]))
+        P1 = self.N1 - self.n1 + 1
+        y = torch.empty((count, P1, self.n0, self.n1), dtype=torch.complex64, device=x.device)
+        with torch.cuda.device(x.device):
+            stream = torch.cuda.current_stream(x.device).cuda_stream
+            check(lib.swdft2d_stream_push(self.handle, x.data_ptr(), x.shape[0],
+                                          y.data_ptr() if count else None, stream),
+                  "swdft2d_stream_push")
+        return y
+
+    def reset(self) -> None:
+        stream = torch.cuda.current_stream().cuda_stream if torch.cuda.is_available() else None
+        check(lib.swdft2d_stream_reset(self.handle, stream), "swdft2d_stream_reset")
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            check(lib.swdft2d_stream_destroy(self.handle), "swdft2d_stream_destroy")
             self.handle = None
 
     def __del__(self):

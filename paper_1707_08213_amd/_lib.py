@@ -48,6 +48,13 @@ SIGNATURES = {
     "swdft2d_write_probe": (_int, [_vp, _i64, _vp]),
     "swdft2d_plan_batched": (_int, [_PLAN_P, _vp, _i64, _int]),
     "swdft2d_tune": (_int, [_vp, _vp, _vp, _vp]),
+    "swdft2d_stream_create": (_int, [_PLAN_P, _i64, _i32, _i32, _int]),
+    "swdft2d_stream_set_norm": (_int, [_vp, _int]),
+    "swdft2d_stream_rows": (_i64, [_vp]),
+    "swdft2d_stream_completes": (_i64, [_vp, _i64]),
+    "swdft2d_stream_push": (_int, [_vp, _vp, _i64, _vp, _vp]),
+    "swdft2d_stream_reset": (_int, [_vp, _vp]),
+    "swdft2d_stream_destroy": (_int, [_vp]),
     "swdft3d_plan": (_int, [_PLAN_P, _i64, _i64, _i64, _i32, _i32, _i32, _int, _i64]),
     "swdft3d_set_norm": (_int, [_vp, _int]),
     "swdft3d_exec": (_int, [_vp, _vp, _vp, _vp]),

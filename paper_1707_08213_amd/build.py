@@ -16,7 +16,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIBRARY = os.path.join(PKG, "libswdft2d.so")
-SOURCES = ["abi.hip", "abi3d.hip", "tree3d_fwd.hip", "batched_host.hip", "tune.hip",
+SOURCES = ["abi.hip", "abi3d.hip", "abi_stream.hip", "tree3d_fwd.hip", "tree_stream.hip",
+           "batched_host.hip", "tune.hip",
            "tree_config.hip", "tree_fwd.hip",
            "write_probe.hip", "tree_adj.hip", "direct_f64.hip", "dense_mfma.hip",
            "dense_mfma_r.hip", "dense_mfma_c.hip", "batched.hip", "batched_tree_r.hip",
@@ -24,7 +25,8 @@ SOURCES = ["abi.hip", "abi3d.hip", "tree3d_fwd.hip", "batched_host.hip", "tune.h
     f"tree_{kind}_n{n}_{t}.hip" for kind in ("fwd", "adj") for n in (1, 2, 4, 8, 16, 32)
     for t in ("r", "c")] + [
     f"tree_fwd_n{n0}_{t}_{n1}.hip" for n0 in (16, 32) for t in ("r", "c") for n1 in (16, 32)] + [
-    f"tree3d_fwd_n{n0}_{t}.hip" for n0 in (2, 4, 8, 16) for t in ("r", "c")]
+    f"tree3d_fwd_n{n0}_{t}.hip" for n0 in (2, 4, 8, 16) for t in ("r", "c")] + [
+    f"tree_stream_n{n0}_{t}.hip" for n0 in (1, 2, 4, 8, 16, 32) for t in ("r", "c")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

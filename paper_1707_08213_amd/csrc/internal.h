@@ -65,6 +65,15 @@ struct Tree3Geom {
   int32_t order;           // tile order: 0 = a contiguous range per XCD, 1 = dispatch order
 };
 
+// One call of a 2D stream: `rows` new input rows after `rows_before` rows.
+struct StreamGeom {
+  int64_t N1, P1;
+  int64_t rows_before;     // rows the stream had received before this call
+  int64_t rows;            // rows carried by this call
+  int32_t nstrips;         // ceil(P1 / window columns per wave)
+  float scale;             // 1 or 1/sqrt(n0 n1)
+};
+
 // Geometry of one adjoint launch. One wave owns a strip of window columns and
 // a slab of S rows of dx; it writes its partial sums for the QW + n1 - 1 x
 // columns its windows touch to the workspace.
@@ -114,6 +123,13 @@ int tree_fwd_default_kg(int n0, int n1);
 bool tree_fwd_kg_supported(int n0, int n1, int kg);
 bool tree_fwd_wv_supported(int n0, int kg, int wv);
 int tree_fwd_resident_waves(int wpc, int ncu);
+
+// streaming 2D tree (tree_stream.hip)
+int tree_stream_state_slots(int n0);  // ring values per lane (m0 n0 / 2, at least 1)
+hipError_t launch_tree_stream(int n0, int n1, bool real_input, const void* x, float2* y,
+                              float2* state, const StreamGeom& g, const TwiddlesF32& tw,
+                              hipStream_t stream);
+hipError_t launch_fill_zero(float2* p, int64_t n, hipStream_t stream);
 
 // 3D forward tree (tree3d_fwd.hip)
 bool tree3_shape_supported(int n0, int n1, int n2);

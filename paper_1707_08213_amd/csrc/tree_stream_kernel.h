@@ -1,0 +1,194 @@
+// Streaming 2D Tree SWDFT for gfx950: the order of Sec. 4.3 in which the
+// loops over trees are innermost and rows arrive one after another. The
+// column levels (Eq. (6)) of a stream only need level u-1 of the last
+// s_u = n0/2^u trees; that state (the 2^(u-1) nodes of each of those trees,
+// m0 n0 / 2 complex values per (q1, k1) stream) stays resident in device
+// memory between calls, so each new input row
+// costs the 2(n0-1) node operations per stream of Eq. (8) and completes one
+// row of P1 windows as soon as it arrives.
+//
+// One wave owns QW = 64/n1 window columns (unsplit streams, KG = 1) and
+// processes the R rows of one call: the row levels (Eq. (5)) per position into
+// LDS, then the column levels with the rings loaded from, and at the end saved
+// to, the resident state. The state is kept in absolute row order: the nodes
+// of tree p at level u-1 sit in tree slot (p mod s_u). The unrolled column phase
+// uses static ring slots (relative step mod s_u), so the load and the save
+// rotate by (first row mod s_u) through computed memory addresses. Steps past
+// the call's last row are skipped (a wave-uniform branch), so calls may
+// carry any number of rows.
+#pragma once
+
+#include "tree_fwd_kernel.h"
+
+namespace swdft {
+namespace tree {
+
+template <int N0W, int N1W, bool REAL>
+__global__ __launch_bounds__(64) void tree_stream_kernel(const void* __restrict__ xv,
+                                                         float2* __restrict__ y,
+                                                         float2* __restrict__ state, StreamGeom g,
+                                                         TwiddlesF32 tw) {
+  using C = TreeCfg<N0W, N1W, REAL, 1>;
+  using CC = ColCfg<N0W, 1>;
+  __shared__ float2 zl[C::LDS_FLOAT2];
+  const int lane = threadIdx.x;
+  const int strip = blockIdx.x;
+  const StreamGeom sg = uniform_copy(g);
+  const float2* w0 = tw.w0;
+  const float2* w1 = tw.w1;
+
+  const int64_t q1_0 = (int64_t)strip * C::QW;
+  const int64_t p_start = sg.rows_before;  // absolute index of the call's first row
+  const int64_t R = sg.rows;
+  const int nchunks = (int)((R + C::CR - 1) / C::CR);
+  // first window row this call completes (windows end at row q0 + n0 - 1)
+  const int64_t q0_first = max((int64_t)0, p_start - (N0W - 1));
+
+  using XT = std::conditional_t<REAL, float, float2>;
+  const XT* x = reinterpret_cast<const XT*>(xv);
+
+  // row-phase roles: lane (r, c)
+  const int rp_r = lane / C::QW;
+  const int rp_c = lane % C::QW;
+  const int64_t rp_q1 = q1_0 + rp_c;
+  // column-phase roles: lane (c, k1)
+  const int cp_c = lane / N1W;
+  const int cp_k1 = lane % N1W;
+  float2* ystrip = y + q1_0 * (N0W * N1W);
+  const int64_t y_row_stride = sg.P1 * (N0W * N1W);
+  const uint32_t strip_bytes =
+      (uint32_t)(min((int64_t)C::QW, sg.P1 - q1_0) * (N0W * N1W * (int)sizeof(float2)));
+  const uint32_t lane_off = (uint32_t)((cp_c * (N0W * N1W) + cp_k1) * (int)sizeof(float2));
+
+  // resident state: slot k of this lane at state[k * state_stride + strip * 64 + lane]
+  float2* st_lane = state + (int64_t)strip * 64 + lane;
+  const int64_t state_stride = (int64_t)sg.nstrips * 64;
+
+  float2 lanefac[CC::M0 + 1];
+  float2 lw[CC::M0 + 1][CC::LW];
+  sfor<0, CC::M0 + 1>([&](auto U) { lanefac[U] = make_float2(1.f, 0.f); });
+
+  // ring of level u-1: s_u tree slots of held(u-1) nodes each; static tree
+  // slot t holds the tree whose absolute row index is congruent to
+  // p_start + t modulo s_u
+  float2 ring[CC::RING_TOTAL];
+  auto state_index = [&](int u, int s, int hp, int t, int j) {
+    return (int64_t)(CC::ring_off(u) + (int)((p_start + t) % s) * hp + j) * state_stride;
+  };
+  sfor<1, CC::M0 + 1>([&](auto U) {
+    constexpr int u = U;
+    constexpr int s = N0W >> u;
+    constexpr int hp = CC::held(u - 1);
+    sfor<0, s>([&](auto T) {
+      sfor<0, hp>([&](auto J) {
+        ring[CC::ring_off(u) + T * hp + J] = st_lane[state_index(u, s, hp, T, J)];
+      });
+    });
+  });
+
+  for (int c = 0; c < nchunks; ++c) {
+    const int64_t rel0 = (int64_t)c * C::CR;  // relative index of the chunk's first row
+    // ---- row phase: CR rows x QW window columns of Z into LDS
+    sfor<0, C::CR / C::R>([&](auto PS) {
+      constexpr int ps = PS;
+      const int64_t rel = rel0 + ps * C::R + rp_r;
+      const bool row_ok = rel < R;
+      float2 v[N1W];
+      sfor<0, N1W>([&](auto D) {
+        constexpr int d = D;
+        const int64_t col = rp_q1 + (N1W - 1 - d);
+        const bool ok = row_ok && col < sg.N1;
+        const int64_t idx = ok ? rel * sg.N1 + col : 0;
+        if constexpr (REAL) {
+          const float t = x[idx];
+          v[d] = make_float2(ok ? t : 0.f, 0.f);
+        } else {
+          const float2 t = x[idx];
+          v[d] = ok ? t : make_float2(0.f, 0.f);
+        }
+      });
+      row_levels<N1W>(v, w1);
+      if (sg.scale != 1.0f) {
+        sfor<0, N1W>([&](auto K) { v[K] = make_float2(v[K].x * sg.scale, v[K].y * sg.scale); });
+      }
+      float2* zrow = zl + (ps * C::R + rp_r) * C::ZROW + rp_c * C::ZS;
+      sfor<0, N1W>([&](auto K) { zrow[K] = v[K]; });
+    });
+    __syncthreads();
+
+    // ---- column phase: the chunk's rows that this call carries
+    sfor<0, C::CR>([&](auto STc) {
+      constexpr int st = STc;
+      if (rel0 + st < R) {
+        const float2 z = zl[st * C::ZROW + cp_c * C::ZS + cp_k1];
+        const int64_t q0 = p_start + rel0 + st - (N0W - 1);
+        const bool row_store = q0 >= 0;
+        const auto out = buf_rsrc(ystrip + (row_store ? q0 - q0_first : 0) * y_row_stride,
+                                  row_store ? strip_bytes : 0u);
+        if constexpr (N0W == 1) {
+          store_buf_nt(out, lane_off, z);
+        } else {
+          column_levels<N0W, 1, st % C::RING>(z, ring, lanefac, lw, w0, [&](auto J, float2 v) {
+            store_buf_nt(out, lane_off + J * N1W * (int)sizeof(float2), v);
+          });
+        }
+      }
+    });
+    __syncthreads();
+  }
+
+  // save the rings in absolute order (the same rotation as the load)
+  sfor<1, CC::M0 + 1>([&](auto U) {
+    constexpr int u = U;
+    constexpr int s = N0W >> u;
+    constexpr int hp = CC::held(u - 1);
+    sfor<0, s>([&](auto T) {
+      sfor<0, hp>([&](auto J) {
+        st_lane[state_index(u, s, hp, T, J)] = ring[CC::ring_off(u) + T * hp + J];
+      });
+    });
+  });
+}
+
+template <int N0W, int N1W, bool REAL>
+hipError_t launch_stream_one(const void* x, float2* y, float2* state, const StreamGeom& g,
+                             const TwiddlesF32& tw, hipStream_t stream) {
+  hipLaunchKernelGGL((tree_stream_kernel<N0W, N1W, REAL>), dim3((unsigned)g.nstrips), dim3(64), 0,
+                     stream, x, y, state, g, tw);
+  return hipGetLastError();
+}
+
+template <int N0W, bool REAL>
+hipError_t launch_stream_n0(int n1, const void* x, float2* y, float2* state, const StreamGeom& g,
+                            const TwiddlesF32& tw, hipStream_t s) {
+  switch (n1) {
+    case 1: return launch_stream_one<N0W, 1, REAL>(x, y, state, g, tw, s);
+    case 2: return launch_stream_one<N0W, 2, REAL>(x, y, state, g, tw, s);
+    case 4: return launch_stream_one<N0W, 4, REAL>(x, y, state, g, tw, s);
+    case 8: return launch_stream_one<N0W, 8, REAL>(x, y, state, g, tw, s);
+    case 16: return launch_stream_one<N0W, 16, REAL>(x, y, state, g, tw, s);
+    case 32: return launch_stream_one<N0W, 32, REAL>(x, y, state, g, tw, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace tree
+
+#define SWDFT_STREAM_DECL(N0W, TAG)                                                            \
+  hipError_t launch_tree_stream_n0_##N0W##_##TAG(int, const void*, float2*, float2*,            \
+                                                 const StreamGeom&, const TwiddlesF32&, hipStream_t);
+SWDFT_STREAM_DECL(1, r)
+SWDFT_STREAM_DECL(1, c)
+SWDFT_STREAM_DECL(2, r)
+SWDFT_STREAM_DECL(2, c)
+SWDFT_STREAM_DECL(4, r)
+SWDFT_STREAM_DECL(4, c)
+SWDFT_STREAM_DECL(8, r)
+SWDFT_STREAM_DECL(8, c)
+SWDFT_STREAM_DECL(16, r)
+SWDFT_STREAM_DECL(16, c)
+SWDFT_STREAM_DECL(32, r)
+SWDFT_STREAM_DECL(32, c)
+#undef SWDFT_STREAM_DECL
+
+}  // namespace swdft

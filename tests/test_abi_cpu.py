@@ -259,3 +259,43 @@ def test_plan3d_validation(N, n, dtype, batch, status):
     else:
         assert h.value is None
     assert lib.swdft3d_plan(None, 8, 8, 8, 2, 2, 2, 0, 1) == S["SWDFT_E_ARG"]
+
+
+def test_stream_validation():
+    h = ctypes.c_void_p()
+    cases = [
+        ((64, 8, 8, _lib.SWDFT_R32), "SWDFT_OK"),
+        ((64, 16, 32, _lib.SWDFT_C32), "SWDFT_OK"),
+        ((0, 8, 8, _lib.SWDFT_R32), "SWDFT_E_ARG"),
+        ((64, 8, 8, 9), "SWDFT_E_ARG"),
+        ((64, 8, 8, _lib.SWDFT_R64), "SWDFT_E_DTYPE"),
+        ((64, 6, 8, _lib.SWDFT_R32), "SWDFT_E_NOT_POW2"),
+        ((4, 8, 8, _lib.SWDFT_R32), "SWDFT_E_WINDOW"),      # n1 > N1
+        ((128, 64, 8, _lib.SWDFT_R32), "SWDFT_E_WINDOW"),   # n0 above 32
+        (((1 << 21) + 1, 8, 8, _lib.SWDFT_R32), "SWDFT_E_OVERFLOW"),
+    ]
+    for args, name in cases:
+        st = lib.swdft2d_stream_create(ctypes.byref(h), *args)
+        assert _lib.STATUS[st] == name, (args, lib.swdft2d_last_error())
+        if st == 0:
+            N1, n0 = args[0], args[1]
+            assert lib.swdft2d_stream_rows(h) == 0
+            for R in (0, 1, n0 - 1, n0, 3 * n0 + 5):
+                assert lib.swdft2d_stream_completes(h, R) == max(0, R - n0 + 1)
+            assert lib.swdft2d_stream_completes(h, -1) == -1
+            # argument errors are reported before anything touches a device
+            assert lib.swdft2d_stream_push(h, 0x10000, -1, 0x90000000, None) == S["SWDFT_E_ARG"]
+            assert lib.swdft2d_stream_push(h, 0x10000, 0, None, None) == 0  # no-op
+            assert lib.swdft2d_stream_push(h, None, 4 * n0, 0x90000000, None) == S["SWDFT_E_ARG"]
+            assert lib.swdft2d_stream_push(h, 0x10000, 4 * n0, None, None) == S["SWDFT_E_ARG"]
+            assert lib.swdft2d_stream_push(h, 0x10002, 4 * n0, 0x90000000, None) == S["SWDFT_E_ALIGN"]
+            assert lib.swdft2d_stream_push(h, 0x10000, 4 * n0, 0x90000004, None) == S["SWDFT_E_ALIGN"]
+            assert lib.swdft2d_stream_push(h, 0x10000, 4 * n0, 0x10008, None) == S["SWDFT_E_ARG"]
+            assert lib.swdft2d_stream_set_norm(h, 3) == S["SWDFT_E_ARG"]
+            assert lib.swdft2d_stream_destroy(h) == 0
+            assert lib.swdft2d_stream_destroy(h) == S["SWDFT_E_PLAN"]
+            assert lib.swdft2d_stream_rows(h) == -1
+        else:
+            assert h.value is None
+    assert lib.swdft2d_stream_create(None, 64, 8, 8, 0) == S["SWDFT_E_ARG"]
+    assert lib.swdft2d_stream_push(None, 0x10000, 4, 0x90000000, None) == S["SWDFT_E_PLAN"]
