@@ -403,6 +403,94 @@ def run_vol128(args, swd, dev) -> dict:
     return out
 
 
+def run_stream1024(args, swd, dev) -> dict:
+    """sin1024's rows pushed through a 2D stream (the real-time order of
+    Sec. 4.3): throughput with 64-row pushes, and the latency of 1-row pushes."""
+    import numpy as np
+    import torch
+
+    import workloads
+    wl = workloads.sin1024()
+    x_np, n0, n1 = wl["x"], wl["n0"], wl["n1"]
+    N0, N1 = x_np.shape
+    P0, P1 = N0 - n0 + 1, N1 - n1 + 1
+    x = torch.from_numpy(x_np).to(dev)
+    stream = torch.cuda.current_stream(dev)
+    s = swd.Stream2D(N1, n0, n1)
+    y = torch.empty((P0, P1, n0, n1), dtype=torch.complex64, device=dev)
+    chunk = 64
+    h = s.handle
+    from paper_1707_08213_amd import _lib
+
+    def one_pass():
+        _lib.check(_lib.lib.swdft2d_stream_reset(h, stream.cuda_stream), "swdft2d_stream_reset")
+        out = 0
+        for r in range(0, N0, chunk):
+            rows = min(chunk, N0 - r)
+            cnt = _lib.lib.swdft2d_stream_completes(h, rows)
+            _lib.check(_lib.lib.swdft2d_stream_push(h, x[r].data_ptr(), rows,
+                                                    y[out].data_ptr() if cnt else None,
+                                                    stream.cuda_stream), "swdft2d_stream_push")
+            out += cnt
+
+    for _ in range(max(1, args.warmup // 5)):
+        one_pass()
+    torch.cuda.synchronize()
+    passes = max(2, args.steps // 10)
+    t0 = time.perf_counter()
+    for _ in range(passes):
+        one_pass()
+    torch.cuda.synchronize()
+    per_pass = (time.perf_counter() - t0) / passes
+    coeffs = P0 * P1 * n0 * n1
+    alg_bytes = coeffs * 8 + N0 * N1 * 4
+    achieved = alg_bytes / per_pass / 1e9
+    # latency of one-row pushes in steady state (each completes one window row)
+    _lib.check(_lib.lib.swdft2d_stream_reset(h, stream.cuda_stream), "swdft2d_stream_reset")
+    first = N0 // 2
+    for r in range(0, first, chunk):
+        rows = min(chunk, first - r)
+        cnt = _lib.lib.swdft2d_stream_completes(h, rows)
+        _lib.check(_lib.lib.swdft2d_stream_push(h, x[r].data_ptr(), rows,
+                                                y[0].data_ptr() if cnt else None,
+                                                stream.cuda_stream), "swdft2d_stream_push")
+    torch.cuda.synchronize()
+    lat = []
+    for r in range(first, first + 64):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        _lib.check(_lib.lib.swdft2d_stream_push(h, x[r].data_ptr(), 1, y[0].data_ptr(),
+                                                stream.cuda_stream), "swdft2d_stream_push")
+        b.record(stream)
+        b.synchronize()
+        lat.append(a.elapsed_time(b) * 1e3)
+    lat.sort()
+    err = None
+    if not args.no_cpu_baseline:
+        import oracle
+        one_pass()
+        torch.cuda.synchronize()
+        q0, q1 = workloads.window_sample(P0, P1, 1024, 2006)
+        got = sampled(y, q0, q1)
+        err = rel(got, oracle.get().swdft2d(x_np.astype(np.float64), n0, n1, windows=(q0, q1)))
+    out = base_record(args, coeffs / per_pass, per_pass * 1e3, "f32", {
+        "workload": "stream1024: the 1024 rows of sin1024 pushed through a 2D stream in 64-row "
+                    "calls (16x16 windows, tree state resident between calls)",
+        "N1": N1, "n0": n0, "n1": n1, "rows": N0, "rows_per_push": chunk, "algo": "stream",
+        "coeffs_per_step": coeffs})
+    out["steps"] = passes
+    out.update({"roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
+                             "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                             "kernel": "tree_stream_kernel<16,16,real> (16 calls per pass)",
+                             "algorithmic_bytes_per_launch": alg_bytes,
+                             "avg_launch_us": per_pass * 1e6},
+                "one_row_push_us": {"median": lat[len(lat) // 2], "min": lat[0],
+                                    "max": lat[-1]},
+                "rel_err": err, "cpu_baseline": None})
+    return out
+
+
 def run_grad256(args, swd, dev) -> dict:
     import numpy as np
     import torch
@@ -517,7 +605,7 @@ def run_uneven64(args, swd, dev) -> dict:
 
 
 WORKLOADS = {"sin1024": run_sin1024, "cplx2048": run_cplx2048, "grad256": run_grad256,
-             "vol128": run_vol128,
+             "vol128": run_vol128, "stream1024": run_stream1024,
              "uneven64": run_uneven64}
 
 
