@@ -46,11 +46,24 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_hash() -> str:
+def code_only(text: str) -> str:
+    """C++ source without comments and with whitespace runs collapsed, so that
+    editing a comment does not invalidate recorded counters."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def kernel_hash(read=None) -> str:
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        if read is None:
+            with open(os.path.join(ROOT, p), encoding="utf-8") as f:
+                text = f.read()
+        else:
+            text = read(p)
+        h.update(code_only(text).encode())
     return h.hexdigest()[:16]
 
 

@@ -7,14 +7,18 @@
 // n0-point DFT of each column of Z, which is the 2D DFT of the window. The
 // final level is the output (Sec. 4.2, last paragraph).
 //
-// Mapping to the hardware (one wave64 per workgroup, waves independent):
-//  * A wave owns QW = 64/n1 adjacent window columns and a slab of S output
-//    rows of one image. Lane (c, k1) of the column phase owns the stream
-//    Z[.][q1_0 + c][k1] and walks it down the slab one input row per step.
+// Mapping to the hardware (workgroups of WV wave64s, independent of each
+// other):
+//  * A workgroup owns a strip of QW = 64/(n1 KG) adjacent window columns and
+//    a slab of S output rows of one image. Lane (c, k1) of the column phase
+//    owns the stream Z[.][q1_0 + c][k1] and walks it down the slab one input
+//    row per step. A stream may be split by k0 residue over KG lanes of a wave
+//    and WV waves of the workgroup (KT = KG WV residues; see ColCfg and
+//    TreeCfg), each part holding 1/KT of the nodes of every tree.
 //  * Column phase (Eq. (6)), in registers: at row p a lane needs level u-1 of
 //    its own tree (p) and of tree p - s_u, s_u = n0 / 2^u. It keeps the last
-//    s_u positions of every level u-1 in a register ring (n0/2 complex values
-//    per level, m0 levels). Rows are processed in chunks whose length is a
+//    s_u positions of every level u-1 in a register ring (n0/(2 KT) complex
+//    values per level and lane, m0 levels). Rows are processed in chunks whose length is a
 //    multiple of the ring period n0/2, and each chunk is fully unrolled, so
 //    every ring slot is a fixed register. Each new row costs the
 //    2 + 4 + ... + n0 = 2(n0-1) node operations of one new tree column
@@ -33,14 +37,15 @@
 //    window (empty for priming rows): the hardware drops out-of-range lanes,
 //    so the store stream has no exec-mask branches. Partial trees near
 //    the top and left edges (Sec. 4.7) read zeros and are never stored.
-//  * Occupancy and tile order: the host may cap the resident waves per CU
-//    (extra dynamic LDS that the kernel does not touch). With one wave per
-//    CU and a wave per whole column of its strip, the resident waves write
-//    one band of consecutive output rows that moves down the image; tiles
-//    then run in dispatch order so that each round of resident waves covers
-//    one contiguous range of strips. Without a cap, workgroup ids are
-//    remapped so that each XCD (own L2) gets a contiguous range of tiles:
-//    neighbouring strips share input columns.
+//  * Occupancy and tile order: the host may cap the resident workgroups per
+//    CU (extra dynamic LDS that the kernel does not touch). With one per CU
+//    and a workgroup per whole column of its strip, the resident waves write
+//    one band of consecutive output rows that moves down the image; when the
+//    tiles need more than one round of resident workgroups they run in
+//    dispatch order, so that each round covers one contiguous range of
+//    strips. Otherwise workgroup ids are remapped so that each XCD (own L2)
+//    gets a contiguous range of tiles: neighbouring strips share input
+//    columns.
 //  * Inputs of the next chunk are loaded (through a buffer resource that
 //    returns zero past the image) before the column phase of the current
 //    chunk, whose stores then separate the loads from their use: the wait
