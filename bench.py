@@ -189,10 +189,24 @@ def oracle_rate(orc, x2d, n0, n1, P0, P1, seconds: float, seed: int):
     t0 = time.perf_counter()
     orc.swdft2d(x2d, n0, n1, windows=(s0, s1))
     dt = time.perf_counter() - t0
-    return {"value": s0.size * n0 * n1 / dt, "unit": "coeffs/s", "cores": orc.num_threads(),
-            "kind": "oracle",
-            "sample": f"{s0.size} of the {P0}x{P1} windows (seeded, corners and edges "
-                      f"included), {s0.size * n0 * n1} coefficients in {dt:.1f} s"}
+    out = {"value": s0.size * n0 * n1 / dt, "unit": "coeffs/s", "cores": orc.num_threads(),
+           "kind": "oracle",
+           "sample": f"{s0.size} of the {P0}x{P1} windows (seeded, corners and edges "
+                     f"included), {s0.size * n0 * n1} coefficients in {dt:.1f} s"}
+    # the same code on one host core, on about a tenth of the time budget
+    threads = orc.num_threads()
+    orc.set_threads(1)
+    try:
+        n1c = int(min(s0.size, max(64, 0.1 * seconds / (per_win * threads))))
+        c0, c1 = workloads.window_sample(P0, P1, n1c, seed + 2)
+        t0 = time.perf_counter()
+        orc.swdft2d(x2d, n0, n1, windows=(c0, c1))
+        dt1 = time.perf_counter() - t0
+    finally:
+        orc.set_threads(threads)
+    out["one_core"] = {"value": c0.size * n0 * n1 / dt1, "unit": "coeffs/s",
+                       "sample": f"{c0.size} windows in {dt1:.1f} s"}
+    return out
 
 
 def base_record(args, value, ms_per_step, dtype, config) -> dict:

@@ -67,10 +67,16 @@ class Oracle:
                                        i64, vp, vp]
         lib.oracle_swdft3d.restype = ctypes.c_int
         lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_threads.restype = None
         self.lib = lib
 
     def num_threads(self) -> int:
         return int(self.lib.oracle_num_threads())
+
+    def set_threads(self, n: int) -> None:
+        """Threads of later OpenMP regions (timing only; results do not depend on it)."""
+        self.lib.oracle_set_threads(int(n))
 
     def swdft2d(self, x, n0: int, n1: int, windows=None, norm: str = "none") -> np.ndarray:
         """Direct 2D SWDFT of one N0 x N1 image (real or complex).

@@ -337,6 +337,8 @@ int oracle_swdft3d(const double* x_re, const double* x_im, int64_t N0, int64_t N
 #ifdef _OPENMP
 #include <omp.h>
 int oracle_num_threads(void) { return omp_get_max_threads(); }
+void oracle_set_threads(int n) { if (n >= 1) omp_set_num_threads(n); }
 #else
 int oracle_num_threads(void) { return 1; }
+void oracle_set_threads(int n) { (void)n; }
 #endif
