@@ -25,6 +25,11 @@
  *            normwise relative error about 5e-6 instead of the tree's 2e-7).
  *   DIRECT_F64 - Eq. (2) evaluated literally per coefficient in FP64
  *            (the comparator; the only algorithm for R64/C64 input).
+ *   SWFFT  - the 2D SWFFT comparator of Table 1 and Fig. 4: a radix-2
+ *            row-column FFT of every window from scratch, nothing shared
+ *            between windows, (n0 n1 / 2) log2(n0 n1) butterflies per window.
+ *            FP32, the same twiddles and butterflies as the tree, so it
+ *            computes the same intermediate values (Sec. 4.6).
  *   AUTO   - TREE for R32/C32, DIRECT_F64 for R64/C64.
  *
  * Memory layout (all row-major, contiguous, device memory owned by the caller):
@@ -75,7 +80,8 @@ typedef enum {
     SWDFT_ALGO_AUTO = 0,
     SWDFT_ALGO_TREE = 1,
     SWDFT_ALGO_DENSE_BF16X2 = 2,
-    SWDFT_ALGO_DIRECT_F64 = 3
+    SWDFT_ALGO_DIRECT_F64 = 3,
+    SWDFT_ALGO_SWFFT = 4
 } swdft_algo_t;
 
 typedef int swdft_status_t;
@@ -110,8 +116,8 @@ swdft_status_t swdft2d_plan(swdft2d_plan_t* out, int64_t N0, int64_t N1, int32_t
 /* Select the output scale. Allowed at any time; affects later calls. */
 swdft_status_t swdft2d_set_norm(swdft2d_plan_t plan, swdft_norm_t norm);
 
-/* Select the algorithm. E_DTYPE if it cannot serve the plan's dtype (TREE and
- * DENSE_BF16X2 serve R32/C32; DIRECT_F64 serves R64/C64, whose callers widen
+/* Select the algorithm. E_DTYPE if it cannot serve the plan's dtype (TREE,
+ * DENSE_BF16X2 and SWFFT serve R32/C32; DIRECT_F64 serves R64/C64, whose callers widen
  * FP32 data to FP64 exactly beforehand); E_WINDOW if DENSE_BF16X2 is asked for
  * a window outside {8,16,32} x {8,16,32}. */
 swdft_status_t swdft2d_set_algo(swdft2d_plan_t plan, swdft_algo_t algo);

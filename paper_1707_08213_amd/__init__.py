@@ -31,7 +31,8 @@ _OUT_DTYPE = {_lib.SWDFT_R32: torch.complex64, _lib.SWDFT_C32: torch.complex64,
               _lib.SWDFT_R64: torch.complex128, _lib.SWDFT_C64: torch.complex128}
 _NORMS = {"none": _lib.SWDFT_NORM_NONE, "ortho": _lib.SWDFT_NORM_ORTHO}
 _ALGOS = {"auto": _lib.SWDFT_ALGO_AUTO, "tree": _lib.SWDFT_ALGO_TREE,
-          "dense_bf16x2": _lib.SWDFT_ALGO_DENSE_BF16X2, "direct_f64": _lib.SWDFT_ALGO_DIRECT_F64}
+          "dense_bf16x2": _lib.SWDFT_ALGO_DENSE_BF16X2, "direct_f64": _lib.SWDFT_ALGO_DIRECT_F64,
+          "swfft": _lib.SWDFT_ALGO_SWFFT}
 
 
 def output_shape(N0: int, N1: int, n0: int, n1: int, batch: int = 1):

@@ -14,7 +14,8 @@ LIBRARY = os.path.join(PKG, "libswdft2d.so")
 
 SWDFT_R32, SWDFT_C32, SWDFT_R64, SWDFT_C64 = 0, 1, 2, 3
 SWDFT_NORM_NONE, SWDFT_NORM_ORTHO = 0, 1
-SWDFT_ALGO_AUTO, SWDFT_ALGO_TREE, SWDFT_ALGO_DENSE_BF16X2, SWDFT_ALGO_DIRECT_F64 = 0, 1, 2, 3
+(SWDFT_ALGO_AUTO, SWDFT_ALGO_TREE, SWDFT_ALGO_DENSE_BF16X2, SWDFT_ALGO_DIRECT_F64,
+ SWDFT_ALGO_SWFFT) = 0, 1, 2, 3, 4
 
 STATUS = {
     0: "SWDFT_OK", 1: "SWDFT_E_ARG", 2: "SWDFT_E_NOT_POW2", 3: "SWDFT_E_WINDOW",

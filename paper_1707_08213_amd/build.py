@@ -19,7 +19,8 @@ LIBRARY = os.path.join(PKG, "libswdft2d.so")
 SOURCES = ["abi.hip", "abi3d.hip", "abi_stream.hip", "tree3d_fwd.hip", "tree_stream.hip",
            "batched_host.hip", "tune.hip",
            "tree_config.hip", "tree_fwd.hip",
-           "write_probe.hip", "tree_adj.hip", "direct_f64.hip", "dense_mfma.hip",
+           "write_probe.hip", "tree_adj.hip", "direct_f64.hip", "swfft_r.hip", "swfft_c.hip",
+           "dense_mfma.hip",
            "dense_mfma_r.hip", "dense_mfma_c.hip", "batched.hip", "batched_tree_r.hip",
            "batched_tree_c.hip", "batched_dense_r.hip", "batched_dense_c.hip"] + [
     f"tree_{kind}_n{n}_{t}.hip" for kind in ("fwd", "adj") for n in (1, 2, 4, 8, 16, 32)

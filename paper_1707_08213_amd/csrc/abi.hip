@@ -238,6 +238,26 @@ swdft::DirectGeom direct_geom(const swdft2d_plan_s* p) {
   return g;
 }
 
+// Window rows per workgroup of the per-window FFT: enough workgroups (about
+// 8192) to fill the chip a few times over, each walking a run of rows.
+swdft::SwfftGeom swfft_geom(const swdft2d_plan_s* p) {
+  swdft::SwfftGeom g{};
+  g.N0 = p->N0;
+  g.N1 = p->N1;
+  g.P0 = p->P0;
+  g.P1 = p->P1;
+  g.x_image_stride = p->N0 * p->N1;
+  g.y_image_stride = p->P0 * p->P1 * p->n0 * p->n1;
+  g.ngroups = (int32_t)ceil_div(p->P1, swdft::swfft_windows_per_group(p->n0, p->n1));
+  const int64_t per_row = (int64_t)g.ngroups * p->batch;
+  const int64_t nslabs = std::min<int64_t>(p->P0, std::max<int64_t>(1, ceil_div(8192, per_row)));
+  g.RS = (int32_t)ceil_div(p->P0, nslabs);
+  g.nslabs = (int32_t)ceil_div(p->P0, g.RS);
+  g.batch = (int32_t)p->batch;
+  g.scale = norm_scale(p->norm, p->n0, p->n1);
+  return g;
+}
+
 bool ranges_overlap(const void* a, int64_t abytes, const void* b, int64_t bbytes) {
   const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
   return a0 < b0 + (uintptr_t)bbytes && b0 < a0 + (uintptr_t)abytes;
@@ -339,6 +359,7 @@ swdft_status_t swdft2d_set_algo(swdft2d_plan_t plan, swdft_algo_t algo) {
     case SWDFT_ALGO_AUTO: break;
     case SWDFT_ALGO_TREE:
     case SWDFT_ALGO_DENSE_BF16X2:
+    case SWDFT_ALGO_SWFFT:
       if (f64_dtype(plan->dtype))
         return fail(SWDFT_E_DTYPE, "algorithm %d computes in FP32 and needs an R32/C32 plan",
                     (int)algo);
@@ -376,6 +397,10 @@ swdft_status_t swdft2d_exec(swdft2d_plan_t plan, const void* x, void* y, hipStre
     case SWDFT_ALGO_DENSE_BF16X2:
       e = swdft::launch_dense_fwd(p->n0, p->n1, real_dtype(p->dtype), x, static_cast<float2*>(y),
                                   dense_geom(p), p->tw32, stream);
+      break;
+    case SWDFT_ALGO_SWFFT:
+      e = swdft::launch_swfft(p->n0, p->n1, real_dtype(p->dtype), x, static_cast<float2*>(y),
+                              swfft_geom(p), p->tw32, stream);
       break;
     case SWDFT_ALGO_DIRECT_F64:
       e = swdft::launch_direct_f64(p->n0, p->n1, real_dtype(p->dtype), x,
@@ -481,6 +506,14 @@ swdft_status_t swdft2d_describe(swdft2d_plan_t plan, char* buf, int32_t len) {
              p->n0, p->n1, (long long)p->N0, (long long)p->N1, (long long)p->batch,
              swdft::dense_columns_per_wave(p->n0, p->n1), g.S, g.nstrips, g.nslabs,
              (long long)g.nstrips * g.nslabs * p->batch);
+  } else if (a == SWDFT_ALGO_SWFFT) {
+    const swdft::SwfftGeom g = swfft_geom(p);
+    snprintf(buf, (size_t)len,
+             "algo=swfft n=%dx%d N=%lldx%lld batch=%lld windows_per_group=%d rows_per_group=%d "
+             "groups=%lld",
+             p->n0, p->n1, (long long)p->N0, (long long)p->N1, (long long)p->batch,
+             swdft::swfft_windows_per_group(p->n0, p->n1), g.RS,
+             (long long)g.ngroups * g.nslabs * p->batch);
   } else {
     snprintf(buf, (size_t)len, "algo=direct_f64 n=%dx%d N=%lldx%lld batch=%lld windows_per_block=%d",
              p->n0, p->n1, (long long)p->N0, (long long)p->N1, (long long)p->batch,

@@ -112,6 +112,19 @@ struct DirectGeom {
   double scale;
 };
 
+// Geometry of one per-window FFT launch (the SWFFT comparator). A workgroup
+// owns a group of window columns and walks RS window rows of one image.
+struct SwfftGeom {
+  int64_t N0, N1, P0, P1;
+  int64_t x_image_stride;  // elements between images of x
+  int64_t y_image_stride;  // float2 between images of y
+  int32_t RS;              // window rows per workgroup
+  int32_t ngroups;         // ceil(P1 / windows per workgroup)
+  int32_t nslabs;          // ceil(P0 / RS)
+  int32_t batch;
+  float scale;             // 1 or 1/sqrt(n0 n1)
+};
+
 // Kernel launchers (defined next to their kernels). They validate nothing:
 // the plan code has checked every argument before calling them.
 hipError_t launch_tree_fwd(int n0, int n1, bool real_input, const void* x, float2* y,
@@ -153,6 +166,10 @@ int dense_columns_per_wave(int n0, int n1);
 hipError_t launch_direct_f64(int n0, int n1, bool real_input, const void* x, double2* y,
                              const DirectGeom& g, const TwiddlesF64& tw, hipStream_t stream);
 int direct_f64_windows_per_block(int n0, int n1);
+
+hipError_t launch_swfft(int n0, int n1, bool real_input, const void* x, float2* y,
+                        const SwfftGeom& g, const TwiddlesF32& tw, hipStream_t stream);
+int swfft_windows_per_group(int n0, int n1);
 
 hipError_t launch_write_probe(float2* y, int64_t n_float2, hipStream_t stream);
 

@@ -128,6 +128,7 @@ def test_destroyed_plan_is_rejected():
 def test_algo_dtype_rules():
     st, h = make_plan(32, 32, 4, 4, _lib.SWDFT_R32)
     assert lib.swdft2d_set_algo(h, _lib.SWDFT_ALGO_TREE) == 0
+    assert lib.swdft2d_set_algo(h, _lib.SWDFT_ALGO_SWFFT) == 0
     assert lib.swdft2d_set_algo(h, _lib.SWDFT_ALGO_DIRECT_F64) == S["SWDFT_E_DTYPE"]
     assert lib.swdft2d_set_algo(h, 17) == S["SWDFT_E_ARG"]
     assert lib.swdft2d_set_norm(h, 5) == S["SWDFT_E_ARG"]
@@ -135,6 +136,7 @@ def test_algo_dtype_rules():
     lib.swdft2d_destroy(h)
     st, h = make_plan(32, 32, 4, 4, _lib.SWDFT_C64)
     assert lib.swdft2d_set_algo(h, _lib.SWDFT_ALGO_TREE) == S["SWDFT_E_DTYPE"]
+    assert lib.swdft2d_set_algo(h, _lib.SWDFT_ALGO_SWFFT) == S["SWDFT_E_DTYPE"]
     assert lib.swdft2d_set_algo(h, _lib.SWDFT_ALGO_DIRECT_F64) == 0
     lib.swdft2d_destroy(h)
 
@@ -145,6 +147,14 @@ def test_describe_and_status_strings():
     assert lib.swdft2d_describe(h, buf, 256) == 0
     d = buf.value.decode()
     assert "algo=tree" in d and "n=16x16" in d
+    assert lib.swdft2d_set_algo(h, _lib.SWDFT_ALGO_SWFFT) == 0
+    assert lib.swdft2d_describe(h, buf, 256) == 0
+    d = buf.value.decode()
+    # 4 windows per 64-lane group, 253 groups per row: 33 slabs of 31 rows (>= 8192 groups)
+    assert "algo=swfft" in d and "windows_per_group=4" in d, d
+    rows = int(d.split("rows_per_group=")[1].split()[0])
+    groups = int(d.split("groups=")[-1].split()[0])
+    assert rows == 31 and groups == 253 * 33, d
     lib.swdft2d_destroy(h)
     for code, name in _lib.STATUS.items():
         assert lib.swdft2d_status_string(code).decode() == name
