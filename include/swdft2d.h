@@ -96,7 +96,9 @@ typedef int swdft_status_t;
 #define SWDFT_E_DEVICE 8      /* a HIP call failed; detail in swdft2d_last_error() */
 #define SWDFT_E_PLAN 9        /* null or destroyed plan, or wrong plan kind */
 
-#define SWDFT_MAX_WINDOW 32   /* largest n0 or n1 a plan accepts */
+#define SWDFT_MAX_WINDOW 64   /* largest n0 or n1 a plan accepts */
+#define SWDFT_MAX_WINDOW_ADJ 32 /* largest n0 or n1 of swdft2d_backward and of
+                                   2D streams */
 #define SWDFT_MAX_ROW 2097152 /* largest N1 a plan accepts: 128 input rows of it
                                  (the most one tile stages) stay within 2 GiB,
                                  so kernels address them with 32-bit offsets */
@@ -134,7 +136,8 @@ swdft_status_t swdft2d_exec(swdft2d_plan_t plan, const void* x, void* y, hipStre
  * respect to x when dy = dL/dRe(y) + i dL/dIm(y). Computed with the levels of
  * Eq. (5)-(6) transposed and run in reverse (gather form: deterministic, no
  * atomics). Supported for R32/C32 plans with TREE (or AUTO); E_DTYPE
- * otherwise. Errors as for exec. Allocates the plan's workspace (partial sums
+ * otherwise. E_WINDOW for n_i above SWDFT_MAX_WINDOW_ADJ (checked first, after
+ * the plan itself). Errors as for exec. Allocates the plan's workspace (partial sums
  * of (64/n1 + n1 - 1) x-columns per strip of 64/n1 window columns, about
  * (1 + n1^2/64) times the size of dx) on first use, or when called on another
  * device, with hipMalloc (E_NOMEM on failure); later calls reuse it. */
@@ -221,7 +224,7 @@ typedef struct swdft2d_stream_s* swdft2d_stream_t;
 
 /* Checks: out != NULL, N1, n0, n1 >= 1 and dtype known (E_ARG); dtype R32 or
  * C32 (E_DTYPE); n0, n1 powers of two (E_NOT_POW2); n1 <= N1 and
- * n_i <= SWDFT_MAX_WINDOW (E_WINDOW); N1 <= SWDFT_MAX_ROW (E_OVERFLOW).
+ * n_i <= SWDFT_MAX_WINDOW_ADJ (E_WINDOW); N1 <= SWDFT_MAX_ROW (E_OVERFLOW).
  * Touches no GPU. The device state, 8 * max(m0 n0 / 2, 1) * 64 bytes per strip
  * of 64/n1 window columns (about 4 m0 n0 n1 (N1 - n1 + 1) bytes), is
  * allocated with hipMalloc at the first push, on the current device, and

@@ -24,8 +24,9 @@ SOURCES = ["abi.hip", "abi3d.hip", "abi_stream.hip", "tree3d_fwd.hip", "tree_str
            "dense_mfma_r.hip", "dense_mfma_c.hip", "batched.hip", "batched_tree_r.hip",
            "batched_tree_c.hip", "batched_dense_r.hip", "batched_dense_c.hip"] + [
     f"tree_{kind}_n{n}_{t}.hip" for kind in ("fwd", "adj") for n in (1, 2, 4, 8, 16, 32)
-    for t in ("r", "c")] + [
-    f"tree_fwd_n{n0}_{t}_{n1}.hip" for n0 in (16, 32) for t in ("r", "c") for n1 in (16, 32)] + [
+    for t in ("r", "c")] + [f"tree_fwd_n64_{t}.hip" for t in ("r", "c")] + [
+    f"tree_fwd_n{n0}_{t}_{n1}.hip" for n0 in (16, 32) for t in ("r", "c") for n1 in (16, 32, 64)] + [
+    f"tree_fwd_n64_{t}_{n1}.hip" for t in ("r", "c") for n1 in (16, 32, 64)] + [
     f"tree3d_fwd_n{n0}_{t}.hip" for n0 in (2, 4, 8, 16) for t in ("r", "c")] + [
     f"tree_stream_n{n0}_{t}.hip" for n0 in (1, 2, 4, 8, 16, 32) for t in ("r", "c")]
 

@@ -416,6 +416,9 @@ swdft_status_t swdft2d_exec(swdft2d_plan_t plan, const void* x, void* y, hipStre
 swdft_status_t swdft2d_backward(swdft2d_plan_t plan, const void* dy, void* dx, hipStream_t stream) {
   if (!is_live(plan)) return fail(SWDFT_E_PLAN, "null or destroyed plan");
   if (plan->kind == 1) return fail(SWDFT_E_PLAN, "backward is not available for batched plans");
+  if (plan->n0 > SWDFT_MAX_WINDOW_ADJ || plan->n1 > SWDFT_MAX_WINDOW_ADJ)
+    return fail(SWDFT_E_WINDOW, "backward supports windows up to %d, not %d x %d",
+                SWDFT_MAX_WINDOW_ADJ, plan->n0, plan->n1);
   const swdft2d_plan_s* p = plan;
   const int64_t xb = p->batch * p->N0 * p->N1 * x_elem_bytes(p->dtype);
   const int64_t yb = swdft2d_output_bytes(plan);

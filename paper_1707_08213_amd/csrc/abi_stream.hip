@@ -95,9 +95,9 @@ swdft_status_t swdft2d_stream_create(swdft2d_stream_t* out, int64_t N1, int32_t 
     return fail(SWDFT_E_NOT_POW2, "window %d x %d is not radix-2", n0, n1);
   if (n1 > N1) return fail(SWDFT_E_WINDOW, "window width %d larger than the row length %lld", n1,
                            (long long)N1);
-  if (n0 > SWDFT_MAX_WINDOW || n1 > SWDFT_MAX_WINDOW)
-    return fail(SWDFT_E_WINDOW, "window %d x %d above the supported maximum %d", n0, n1,
-                SWDFT_MAX_WINDOW);
+  if (n0 > SWDFT_MAX_WINDOW_ADJ || n1 > SWDFT_MAX_WINDOW_ADJ)
+    return fail(SWDFT_E_WINDOW, "window %d x %d above the streams' maximum %d", n0, n1,
+                SWDFT_MAX_WINDOW_ADJ);
   if (N1 > SWDFT_MAX_ROW)
     return fail(SWDFT_E_OVERFLOW, "row length %lld above the supported maximum %d",
                 (long long)N1, SWDFT_MAX_ROW);

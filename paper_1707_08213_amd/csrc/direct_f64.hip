@@ -19,7 +19,8 @@ constexpr int kDirectThreads = 256;
 constexpr int kDirectTileElems = 2048;  // LDS budget for the input tile (elements)
 
 __host__ __device__ constexpr int direct_windows_per_block(int n0, int n1) {
-  // enough coefficients for every thread, tile fits the LDS budget
+  // enough coefficients for every thread, tile within the LDS budget (one
+  // window's n0 x n1 tile always; 64 KiB at n0 = n1 = 64)
   int wb = 1;
   while (wb < 64 && wb * n0 * n1 < 8 * kDirectThreads &&
          n0 * (2 * wb + n1 - 1) <= kDirectTileElems)
@@ -27,16 +28,23 @@ __host__ __device__ constexpr int direct_windows_per_block(int n0, int n1) {
   return wb;
 }
 
+// LDS of one block: the n0 x (wb + n1 - 1) input tile, then both twiddle
+// vectors.
+__host__ __device__ constexpr int direct_tile_elems(int n0, int n1, int wb) {
+  return n0 * (wb + n1 - 1);
+}
+
 template <bool REAL>
 __global__ __launch_bounds__(kDirectThreads) void direct_f64_kernel(const void* __restrict__ xv,
                                                                     double2* __restrict__ y,
                                                                     DirectGeom g, TwiddlesF64 tw,
                                                                     int wb) {
-  __shared__ double2 xs[kDirectTileElems];
-  __shared__ double2 w0s[kMaxWindow];
-  __shared__ double2 w1s[kMaxWindow];
-
+  extern __shared__ double2 lds[];
   const int n0 = g.n0, n1 = g.n1;
+  double2* xs = lds;
+  double2* w0s = lds + direct_tile_elems(n0, n1, wb);
+  double2* w1s = w0s + n0;
+
   int id = blockIdx.x;
   const int tile1 = id % g.ntiles1;
   id /= g.ntiles1;
@@ -98,11 +106,12 @@ hipError_t launch_direct_f64(int n0, int n1, bool real_input, const void* x, dou
   const int wb = direct_windows_per_block(n0, n1);
   const int64_t nb = (int64_t)g.batch * g.P0 * g.ntiles1;
   if (nb > 0x7fffffff) return hipErrorInvalidConfiguration;
+  const size_t lds = (size_t)(direct_tile_elems(n0, n1, wb) + n0 + n1) * sizeof(double2);
   if (real_input) {
-    hipLaunchKernelGGL(direct_f64_kernel<true>, dim3((unsigned)nb), dim3(kDirectThreads), 0,
+    hipLaunchKernelGGL(direct_f64_kernel<true>, dim3((unsigned)nb), dim3(kDirectThreads), lds,
                        stream, x, y, g, tw, wb);
   } else {
-    hipLaunchKernelGGL(direct_f64_kernel<false>, dim3((unsigned)nb), dim3(kDirectThreads), 0,
+    hipLaunchKernelGGL(direct_f64_kernel<false>, dim3((unsigned)nb), dim3(kDirectThreads), lds,
                        stream, x, y, g, tw, wb);
   }
   return hipGetLastError();

@@ -7,7 +7,7 @@
 
 namespace swdft {
 
-constexpr int kMaxWindow = 32;
+constexpr int kMaxWindow = 64;
 
 // Twiddle vectors Omega^0 (length n0) and Omega^1 (length n1) of Sec. 4.2,
 // Omega^i[m] = exp(-2 pi i m / n_i), generated in FP64 and rounded once to

@@ -174,6 +174,7 @@ hipError_t launch_n0(int n1, const void* x, float2* y, const SwfftGeom& g, const
     case 8: return launch_one<N0W, 8, REAL>(x, y, g, tw, s);
     case 16: return launch_one<N0W, 16, REAL>(x, y, g, tw, s);
     case 32: return launch_one<N0W, 32, REAL>(x, y, g, tw, s);
+    case 64: return launch_one<N0W, 64, REAL>(x, y, g, tw, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -188,6 +189,7 @@ hipError_t launch(int n0, int n1, const void* x, float2* y, const SwfftGeom& g,
     case 8: return launch_n0<8, REAL>(n1, x, y, g, tw, s);
     case 16: return launch_n0<16, REAL>(n1, x, y, g, tw, s);
     case 32: return launch_n0<32, REAL>(n1, x, y, g, tw, s);
+    case 64: return launch_n0<64, REAL>(n1, x, y, g, tw, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -108,6 +108,7 @@ int32_t tree_wv(const swdft2d_plan_s* p, int kg, int wpc) {
   int wv = p->tree_wv > 0 ? p->tree_wv : env_int("SWDFT_TREE_WV", 0);
   if (wv <= 0) wv = (wpc == 1 && two_waves_by_default(p->n0, p->n1, kg)) ? 2 : 1;
   if (!swdft::tree_fwd_wv_supported(p->n0, kg, wv)) wv = 1;
+  if (!swdft::tree_fwd_wv_supported(p->n0, kg, wv)) wv = 2;  // n0 = 64 unsplit: two waves only
   return wv;
 }
 

@@ -19,19 +19,17 @@ int tree_fwd_rows_per_chunk(int n0, int n1, int kg, int wv) {
 // output rows per wave need more waves in flight; and for n1 = 8, where the
 // two lanes of a stream write adjacent 64-byte k0 rows, so each store
 // instruction covers whole 128-byte lines.
+// n0 = 64 is built with one split per n1 (tree::tree_kg64).
 int tree_fwd_default_kg(int n0, int n1) {
+  if (n0 == 64) return tree::tree_kg64(n1);
   return (n0 >= 8 && n1 <= 32 && (n0 == 32 || n0 == 8 || n1 == 8)) ? 2 : 1;
 }
 
 int tree_fwd_resident_waves(int wpc, int ncu) { return wpc > 0 && ncu > 0 ? wpc * ncu : 0; }
 
-bool tree_fwd_wv_supported(int n0, int kg, int wv) {
-  return wv == 1 || (wv == 2 && tree::tree_has_wv2(n0, kg));
-}
+bool tree_fwd_wv_supported(int n0, int kg, int wv) { return tree::tree_wv_built(n0, kg, wv); }
 
-bool tree_fwd_kg_supported(int n0, int n1, int kg) {
-  return kg == 1 || (kg == 2 && n0 >= 8 && n1 <= 32);
-}
+bool tree_fwd_kg_supported(int n0, int n1, int kg) { return tree::tree_kg_built(n0, n1, kg); }
 
 hipError_t launch_tree_fwd(int n0, int n1, bool real_input, const void* x, float2* y,
                            const TreeGeom& g, const TwiddlesF32& tw, hipStream_t stream) {
@@ -42,6 +40,7 @@ hipError_t launch_tree_fwd(int n0, int n1, bool real_input, const void* x, float
     case 8: return real_input ? launch_tree_fwd_n0_8_r(n1, x, y, g, tw, stream) : launch_tree_fwd_n0_8_c(n1, x, y, g, tw, stream);
     case 16: return real_input ? launch_tree_fwd_n0_16_r(n1, x, y, g, tw, stream) : launch_tree_fwd_n0_16_c(n1, x, y, g, tw, stream);
     case 32: return real_input ? launch_tree_fwd_n0_32_r(n1, x, y, g, tw, stream) : launch_tree_fwd_n0_32_c(n1, x, y, g, tw, stream);
+    case 64: return real_input ? launch_tree_fwd_n0_64_r(n1, x, y, g, tw, stream) : launch_tree_fwd_n0_64_c(n1, x, y, g, tw, stream);
     default: return hipErrorInvalidValue;
   }
 }

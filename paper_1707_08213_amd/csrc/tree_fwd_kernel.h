@@ -337,17 +337,29 @@ __device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float
   const int rp_c = lane % C::QW;
   const int64_t rp_q1 = q1_0 + rp_c;
   // byte offset of the lane's input x[r][q1 + n1 - 1 - d] within a chunk of
-  // rows; columns past the image edge read zero (Sec. 4.7)
-  uint32_t x_off[N1W];
-  sfor<0, N1W>([&](auto D) {
-    constexpr int d = D;
+  // rows; columns past the image edge read zero (Sec. 4.7). Kept in registers
+  // up to n1 = 32; the 64 of n1 = 64 are recomputed at each load.
+  constexpr bool kKeepOffsets = N1W <= 32;
+  uint32_t x_off_keep[kKeepOffsets ? N1W : 1];
+  auto x_off_of = [&](int d) -> uint32_t {
     const int64_t col = rp_q1 + (N1W - 1 - d);
-    x_off[d] = col < g.N1 ? (uint32_t)(((int64_t)rp_r * g.N1 + col) * EB) : kOutOfRange;
-  });
+    return col < g.N1 ? (uint32_t)(((int64_t)rp_r * g.N1 + col) * EB) : kOutOfRange;
+  };
+  if constexpr (kKeepOffsets) sfor<0, N1W>([&](auto D) { x_off_keep[D] = x_off_of(D); });
+  auto x_off = [&](auto D) -> uint32_t {
+    if constexpr (kKeepOffsets) {
+      return x_off_keep[D];
+    } else {
+      return x_off_of(D);
+    }
+  };
   // Raw inputs of this wave's passes of one chunk (rows crow + (wv * PPW +
   // ps) * R + r), loaded a chunk ahead so that their latency hides behind the
-  // column phase of the previous chunk. Rows past the image bottom lie
-  // outside the resource and read zero.
+  // column phase of the previous chunk (up to n1 = 32; at n1 = 64 the
+  // registers are worth more to the rings, and the loads come right before
+  // the row phase). Rows past the image bottom lie outside the resource and
+  // read zero.
+  constexpr bool kPrefetch = N1W <= 32;
   constexpr int PASSES = C::PPW;
   XT xin[PASSES][N1W];
   auto load_chunk = [&](int64_t crow) {
@@ -359,7 +371,7 @@ __device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float
       constexpr int ps = PS;
       sfor<0, N1W>([&](auto D) {
         constexpr int d = D;
-        xin[ps][d] = load_buf<REAL>(rs, x_off[d] + wave_off + (uint32_t)(ps * C::R * g.N1 * EB));
+        xin[ps][d] = load_buf<REAL>(rs, x_off(D) + wave_off + (uint32_t)(ps * C::R * g.N1 * EB));
       });
     });
   };
@@ -436,7 +448,7 @@ __device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float
   for (int c = 0; c < nchunks; ++c) {
     const int64_t crow = row0 + (int64_t)c * C::CR;
     // past the last chunk this reads zeros and touches no memory
-    load_chunk(crow + C::CR);
+    if constexpr (kPrefetch) load_chunk(crow + C::CR);
     __builtin_amdgcn_sched_barrier(0);
 
     // ---- column phase: CR steps down the slab, one input row each. The Z
@@ -465,6 +477,7 @@ __device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float
     });
     __syncthreads();
     if (c + 1 < nchunks) {
+      if constexpr (!kPrefetch) load_chunk(crow + C::CR);
       row_phase();
       __syncthreads();
     }
@@ -498,6 +511,25 @@ inline unsigned occupancy_lds(int wpc, int lds_cu, unsigned static_lds) {
 // default and the wave's issue rate bounds the tile).
 constexpr bool tree_has_wv2(int n0, int kg) { return n0 >= 16 && kg * 2 < n0; }
 
+// Lanes per stream of the n0 = 64 kernels: as many as one wave's 64 lanes
+// allow (n1 * KG <= 64), at most 8. The register rings then hold 68 (KG = 8),
+// 80 (KG = 4) or 112 (KG = 2) complex values per lane instead of the 192 of an
+// unsplit stream. n0 = 64 is built for this split only.
+constexpr int tree_kg64(int n1) { return n1 >= 64 ? 1 : (64 / n1 > 8 ? 8 : 64 / n1); }
+
+// Lane splits built for each window shape.
+constexpr bool tree_kg_built(int n0, int n1, int kg) {
+  return n0 == 64 ? kg == tree_kg64(n1) : (kg == 1 || (kg == 2 && n0 >= 8 && n1 <= 32));
+}
+
+// Waves per strip built for each split: one wave unless the stream would
+// stay whole (n0 = 64, n1 = 64, whose rings then need two waves), two where
+// tree_has_wv2 allows.
+constexpr bool tree_wv_built(int n0, int kg, int wv) {
+  return wv == 1 ? (n0 < 64 || kg > 1)
+                 : wv == 2 && tree_has_wv2(n0, kg);
+}
+
 template <int N0W, int N1W, bool REAL, int KG, int WV>
 hipError_t launch_cfg(const void* x, float2* y, const TreeGeom& g, const TwiddlesF32& tw,
                       hipStream_t stream) {
@@ -512,21 +544,31 @@ hipError_t launch_cfg(const void* x, float2* y, const TreeGeom& g, const Twiddle
 template <int N0W, int N1W, bool REAL, int KG>
 hipError_t launch_kg(const void* x, float2* y, const TreeGeom& g, const TwiddlesF32& tw,
                      hipStream_t stream) {
-  if constexpr (tree_has_wv2(N0W, KG)) {
+  if constexpr (tree_wv_built(N0W, KG, 2)) {
     if (g.wv == 2) return launch_cfg<N0W, N1W, REAL, KG, 2>(x, y, g, tw, stream);
   }
-  if (g.wv != 1) return hipErrorInvalidValue;
-  return launch_cfg<N0W, N1W, REAL, KG, 1>(x, y, g, tw, stream);
+  if constexpr (tree_wv_built(N0W, KG, 1)) {
+    if (g.wv == 1) return launch_cfg<N0W, N1W, REAL, KG, 1>(x, y, g, tw, stream);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <int N0W, int N1W, bool REAL>
 hipError_t launch_one(const void* x, float2* y, const TreeGeom& g, const TwiddlesF32& tw,
                       hipStream_t stream) {
-  if constexpr (N0W >= 8 && N1W <= 32) {
+  if constexpr (tree_kg_built(N0W, N1W, 1)) {
+    if (g.kg == 1) return launch_kg<N0W, N1W, REAL, 1>(x, y, g, tw, stream);
+  }
+  if constexpr (tree_kg_built(N0W, N1W, 2)) {
     if (g.kg == 2) return launch_kg<N0W, N1W, REAL, 2>(x, y, g, tw, stream);
   }
-  if (g.kg != 1) return hipErrorInvalidValue;
-  return launch_kg<N0W, N1W, REAL, 1>(x, y, g, tw, stream);
+  if constexpr (tree_kg_built(N0W, N1W, 4)) {
+    if (g.kg == 4) return launch_kg<N0W, N1W, REAL, 4>(x, y, g, tw, stream);
+  }
+  if constexpr (tree_kg_built(N0W, N1W, 8)) {
+    if (g.kg == 8) return launch_kg<N0W, N1W, REAL, 8>(x, y, g, tw, stream);
+  }
+  return hipErrorInvalidValue;
 }
 
 // One translation unit per (n0, input type) instantiates launchers for every n1.
@@ -540,6 +582,7 @@ hipError_t launch_n0(int n1, const void* x, float2* y, const TreeGeom& g, const 
     case 8: return launch_one<N0W, 8, REAL>(x, y, g, tw, s);
     case 16: return launch_one<N0W, 16, REAL>(x, y, g, tw, s);
     case 32: return launch_one<N0W, 32, REAL>(x, y, g, tw, s);
+    case 64: return launch_one<N0W, 64, REAL>(x, y, g, tw, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -561,6 +604,8 @@ SWDFT_FWD_DECL(16, r)
 SWDFT_FWD_DECL(16, c)
 SWDFT_FWD_DECL(32, r)
 SWDFT_FWD_DECL(32, c)
+SWDFT_FWD_DECL(64, r)
+SWDFT_FWD_DECL(64, c)
 #undef SWDFT_FWD_DECL
 
 }  // namespace swdft

@@ -1,5 +1,5 @@
-// Forward tree kernels with n0 = 32, real input (every n1; n1 = 16 and
-// 32 are instantiated in tree_fwd_n32_r_16.hip and _32.hip so that the
+// Forward tree kernels with n0 = 32, real input (every n1; n1 = 16, 32
+// and 64 are instantiated in tree_fwd_n32_r_16.hip, _32.hip and _64.hip so that the
 // largest kernels compile in parallel); see tree_fwd_kernel.h.
 #include "tree_fwd_kernel.h"
 
@@ -7,6 +7,7 @@ namespace swdft {
 namespace tree {
 extern template hipError_t launch_one<32, 16, true>(const void*, float2*, const TreeGeom&, const TwiddlesF32&, hipStream_t);
 extern template hipError_t launch_one<32, 32, true>(const void*, float2*, const TreeGeom&, const TwiddlesF32&, hipStream_t);
+extern template hipError_t launch_one<32, 64, true>(const void*, float2*, const TreeGeom&, const TwiddlesF32&, hipStream_t);
 }  // namespace tree
 
 hipError_t launch_tree_fwd_n0_32_r(int n1, const void* x, float2* y, const TreeGeom& g, const TwiddlesF32& tw, hipStream_t s) {

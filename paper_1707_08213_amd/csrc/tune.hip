@@ -156,7 +156,7 @@ swdft_status_t tune_single(swdft2d_plan_s* p, const void* x, void* y, hipStream_
   if (allow_tree) {
     // slabs: the automatic choice for each cap, the whole column, and about
     // 256 to 4096 tiles; caps: none, one or two resident waves per CU
-    for (int kg : {1, 2}) {
+    for (int kg : {1, 2, 4, 8}) {
       if (!tree_fwd_kg_supported(p->n0, p->n1, kg)) continue;
       const int cr = tree_fwd_rows_per_chunk(p->n0, p->n1, kg);
       const int64_t columns =

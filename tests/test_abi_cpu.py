@@ -49,7 +49,10 @@ def make_plan(N0, N1, n0, n1, dtype=_lib.SWDFT_R32, batch=1):
     ((64, 64, 12, 4, 0, 1), "SWDFT_E_NOT_POW2"),
     ((64, 64, 4, 3, 0, 1), "SWDFT_E_NOT_POW2"),
     ((8, 64, 16, 4, 0, 1), "SWDFT_E_WINDOW"),
-    ((128, 128, 64, 4, 0, 1), "SWDFT_E_WINDOW"),
+    ((128, 128, 64, 4, 0, 1), "SWDFT_OK"),
+    ((100, 100, 64, 64, 0, 1), "SWDFT_OK"),
+    ((256, 256, 128, 4, 0, 1), "SWDFT_E_WINDOW"),
+    ((256, 256, 4, 128, 0, 1), "SWDFT_E_WINDOW"),
     ((1 << 40, 1 << 40, 32, 32, 0, 1), "SWDFT_E_OVERFLOW"),
     ((1 << 20, 1 << 20, 32, 32, 0, 1 << 20), "SWDFT_E_OVERFLOW"),
     ((64, 1 << 21, 16, 16, 1, 1), "SWDFT_OK"),            # longest row a plan accepts
@@ -309,3 +312,37 @@ def test_stream_validation():
             assert h.value is None
     assert lib.swdft2d_stream_create(None, 64, 8, 8, 0) == S["SWDFT_E_ARG"]
     assert lib.swdft2d_stream_push(None, 0x10000, 4, 0x90000000, None) == S["SWDFT_E_PLAN"]
+
+
+@pytest.mark.parametrize("n0,n1,kg,cols,wv", [
+    (64, 64, 1, 1, 2), (64, 32, 2, 1, 1), (64, 16, 4, 1, 1), (64, 8, 8, 1, 1), (64, 4, 8, 2, 1),
+    (64, 1, 8, 8, 1), (32, 64, 1, 1, 1), (4, 64, 1, 1, 1)])
+def test_window64_tree_shapes(n0, n1, kg, cols, wv):
+    """n0 = 64 splits each stream over KG = min(8, 64/n1) lanes; 64 x 64, whose
+    stream stays whole, runs two waves per strip."""
+    st, h = make_plan(200, 300, n0, n1)
+    assert st == 0
+    buf = ctypes.create_string_buffer(512)
+    assert lib.swdft2d_describe(h, buf, 512) == 0
+    d = buf.value.decode()
+    assert f"kg={kg} " in d and f"cols_per_wave={cols} " in d and f"waves_per_strip={wv} " in d, d
+    lib.swdft2d_destroy(h)
+
+
+def test_window64_limits_of_other_paths():
+    """Backward and streams stop at SWDFT_MAX_WINDOW_ADJ = 32, the dense variant
+    at 32; the FP64 direct kernel and the per-window FFT take 64."""
+    st, h = make_plan(100, 100, 64, 8)
+    assert st == 0
+    assert lib.swdft2d_backward(h, None, None, None) == S["SWDFT_E_WINDOW"]
+    assert lib.swdft2d_set_algo(h, _lib.SWDFT_ALGO_DENSE_BF16X2) == S["SWDFT_E_WINDOW"]
+    assert lib.swdft2d_set_algo(h, _lib.SWDFT_ALGO_SWFFT) == 0
+    lib.swdft2d_destroy(h)
+    st, h = make_plan(100, 100, 64, 64, _lib.SWDFT_R64)
+    assert st == 0 and lib.swdft2d_set_algo(h, _lib.SWDFT_ALGO_DIRECT_F64) == 0
+    lib.swdft2d_destroy(h)
+    s = ctypes.c_void_p()
+    assert lib.swdft2d_stream_create(ctypes.byref(s), 100, 64, 8, _lib.SWDFT_R32) == S["SWDFT_E_WINDOW"]
+    assert lib.swdft2d_stream_create(ctypes.byref(s), 100, 8, 64, _lib.SWDFT_R32) == S["SWDFT_E_WINDOW"]
+    assert lib.swdft2d_stream_create(ctypes.byref(s), 100, 32, 32, _lib.SWDFT_R32) == 0
+    assert lib.swdft2d_stream_destroy(s) == 0

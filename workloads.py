@@ -25,7 +25,7 @@ from __future__ import annotations
 import numpy as np
 
 WORKLOAD_SEEDS = {"small64": 1, "sin1024": 2, "cplx2048": 3, "uneven64": 4, "grad256": 5,
-                  "vol128": 6}
+                  "vol128": 6, "fig4": 7}
 
 UNEVEN_SIDES = (128, 256, 512, 1024)
 UNEVEN_WINDOWS = ((8, 8), (16, 16), (32, 32), (8, 32))
