@@ -18,6 +18,11 @@ Other workloads (one JSON line each, same fields where they apply):
              L = sum w |A|^2 (band mask w); the adjoint kernel is read-bound.
   uneven64 - 64 real FP32 images of uneven sizes and window shapes in one
              batched graph launch, after autotuning.
+
+``--fig4`` runs the speed comparison of Fig. 4 instead (a markdown table, no
+JSON line): square windows n = 4..64 over a 100 x 100 real array, and over a
+1024 x 1024 one, through the FP64 direct form of Eq. (2), the per-window FFT
+and the tree.
 """
 from __future__ import annotations
 
@@ -168,6 +173,21 @@ def time_launches(fn, steps: int, stream):
     wall = time.perf_counter() - t0
     durs = [s.elapsed_time(e) for s, e in zip(starts, ends)]
     return sum(durs) / len(durs), wall, durs
+
+
+def time_batch(fn, steps: int, stream) -> float:
+    """Average duration (ms) of `steps` back-to-back calls from one event
+    pair on `stream`."""
+    import torch
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    end.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps
 
 
 def roofline(alg_bytes: int, avg_ms: float, kernel: str, traffic=None) -> dict:
@@ -636,6 +656,84 @@ WORKLOADS = {"sin1024": run_sin1024, "cplx2048": run_cplx2048, "grad256": run_gr
              "uneven64": run_uneven64}
 
 
+FIG4_WINDOWS = (4, 8, 16, 32, 64)
+# ops per coefficient (Table 1 over n0 n1 outputs per window): complex
+# multiply-adds of Eq. (2), butterflies of a radix-2 2D FFT, node operations
+# of the tree (Eq. (8))
+FIG4_OPS = {"direct_f64": lambda n: n * n, "swfft": lambda n: (2 * (n.bit_length() - 1)) / 2,
+            "tree": lambda n: 2 * (n * n - 1) / (n * n)}
+
+
+def run_fig4(args, swd, dev) -> str:
+    """Fig. 4 on the GPU: a seeded N(0,1) real array of 100 x 100 (the paper's
+    size) and of 1024 x 1024, square windows n = 4..64, each through the FP64
+    direct form of Eq. (2) (on the FP32 values widened exactly), the FP32
+    per-window FFT and the FP32 tree. Times are averages of HIP event pairs
+    around back-to-back launches; errors are normwise relative to the FP64
+    direct output (to the per-window FFT where the direct form would take
+    seconds per call)."""
+    import numpy as np
+    import torch
+
+    import workloads
+    stream = torch.cuda.current_stream(dev)
+    lines = ["| N | n | algorithm | dtype | ops/coeff | us/call | coeffs/s | output GB/s | "
+             "tree speedup | rel err |",
+             "|---|---|---|---|---|---|---|---|---|---|"]
+    for N in (100, 1024):
+        x32 = torch.from_numpy(workloads.normal_real((N, N), workloads.WORKLOAD_SEEDS["fig4"]))
+        x32 = x32.to(dev)
+        for n in FIG4_WINDOWS:
+            P = N - n + 1
+            coeffs = P * P * n * n
+            res = {}
+            ref = None
+            for algo in ("direct_f64", "swfft", "tree"):
+                est_s = coeffs * n * n / 4e12 if algo == "direct_f64" else 0.0
+                if est_s > 1.0:
+                    log(f"fig4 N={N} n={n} {algo}: skipped (about {est_s:.0f} s per call)")
+                    continue
+                x = (x32.double() if algo == "direct_f64" else x32).unsqueeze(0)
+                plan = swd.Plan(N, N, n, n, dtype=x.dtype, batch=1, algo=algo)
+                y = torch.empty(plan.out_shape, dtype=plan.out_dtype, device=dev)
+                plan.forward(x, out=y)
+                torch.cuda.synchronize()
+                xp, yp, sp = x.data_ptr(), y.data_ptr(), stream.cuda_stream
+
+                def call():
+                    plan.exec_ptr(xp, yp, sp)
+                one, _, _ = time_launches(call, 1, stream)
+                steps = int(min(args.steps * 10, max(3, 0.5e3 / max(one, 1e-3))))
+                for _ in range(min(args.warmup, steps)):
+                    call()
+                # one event pair around back-to-back launches: the queue stays
+                # full, so small calls are timed on the device, not the host
+                avg_ms = time_batch(call, steps, stream)
+                err = None
+                if ref is None:
+                    ref = y  # the first algorithm run is the reference
+                else:
+                    d = (y.to(ref.dtype) - ref).abs().max() / ref.abs().max()
+                    err = float(d)
+                res[algo] = (avg_ms, err, plan.describe())
+                log(f"fig4 N={N} n={n} {algo}: {avg_ms * 1e3:.1f} us/call over {steps} calls"
+                    + (f", rel err {err:.2e}" if err is not None else ""))
+                if y is not ref:
+                    del y
+            del ref
+            torch.cuda.empty_cache()
+            t_tree = res["tree"][0]
+            for algo, (avg_ms, err, _) in res.items():
+                dtype = "f64" if algo == "direct_f64" else "f32"
+                ob = coeffs * (16 if algo == "direct_f64" else 8)
+                lines.append(
+                    f"| {N} | {n} | {algo} | {dtype} | {FIG4_OPS[algo](n):.3g} | "
+                    f"{avg_ms * 1e3:.1f} | {coeffs / (avg_ms * 1e-3):.3e} | "
+                    f"{ob / (avg_ms * 1e-3) / 1e9:.0f} | {avg_ms / t_tree:.2f} | "
+                    f"{'reference' if err is None else f'{err:.1e}'} |")
+    return "\n".join(lines)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -651,6 +749,8 @@ def main() -> int:
                          "hardware byte counters)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="summarise two rocprofv3 --pmc databases and exit (no GPU needed)")
+    ap.add_argument("--fig4", action="store_true",
+                    help="run the Fig. 4 speed comparison (markdown table) instead")
     ap.add_argument("--trace-summary", metavar="TRACE_DB",
                     help="summarise a rocprofv3 --kernel-trace database and exit (no GPU needed)")
     args = ap.parse_args()
@@ -673,6 +773,9 @@ def main() -> int:
     import paper_1707_08213_amd as swd
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.fig4:
+        print(run_fig4(args, swd, dev), flush=True)
+        return 0
     names = sorted(WORKLOADS) if args.workload == "all" else [args.workload]
     if "sin1024" in names:
         names.remove("sin1024")

@@ -19,7 +19,8 @@
 //  1. for i < n0: runs the n1-point FFT of row i of window w and leaves it in
 //     LDS, Z[w][i][k1];
 //  2. for i < n1: runs the n0-point FFT of column k1 = i of Z[w] and stores
-//     y[q0][q1_w][k0][k1] for every k0 (non-temporal).
+//     y[q0][q1_w][k0][k1] for every k0 (non-temporal from n1 = 16 on, where
+//     a store covers whole 128-byte lines).
 #pragma once
 
 #include "tree_fwd_kernel.h"
@@ -146,8 +147,15 @@ __global__ __launch_bounds__(64) void swfft_kernel(const void* __restrict__ xv,
       sfor<0, N0W>([&](auto J) { u[J] = zcol[J * C::ZS]; });
       fft_dit<N0W>(u, tw.w0);
       if (win_ok) {
+        // non-temporal where a store covers whole 128-byte lines of a window
         float2* dst = yimg + ((q0 * g.P1 + q1) * N0W) * N1W + i;
-        sfor<0, N0W>([&](auto K) { tree::store_nt(dst + K * N1W, u[K]); });
+        sfor<0, N0W>([&](auto K) {
+          if constexpr (N1W >= 16) {
+            tree::store_nt(dst + K * N1W, u[K]);
+          } else {
+            dst[K * N1W] = u[K];
+          }
+        });
       }
     }
     __syncthreads();  // Z is read before the next row's tile overwrites it

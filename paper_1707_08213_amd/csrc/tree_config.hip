@@ -126,6 +126,12 @@ int32_t tree_slab(const swdft2d_plan_s* p, int kg, int wv, const TreeCap& cap) {
     } else {
       S = ceil_div(p->P0 * nstrips * p->batch, 4096);
       S = std::max<int64_t>(S, 4 * (int64_t)(p->n0 - 1));
+      // Small images: rather one chunk per slab (priming rows and all) than
+      // fewer tiles than CUs, whose sequential walks down the slab then set
+      // the time (100 x 100 / 16 x 16 has 22 strips: 44 tiles of 79 rows, or
+      // 132 of 31 with one-chunk slabs).
+      const int64_t ncu = cu_count() > 0 ? cu_count() : 256;
+      if (nstrips * p->batch * ceil_div(p->P0, ceil_div(S, cr) * cr) < ncu) S = cr;
     }
   }
   S = std::max<int64_t>(S, cr);

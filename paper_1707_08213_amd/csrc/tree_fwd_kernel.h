@@ -29,8 +29,9 @@
 //    recomputed by this lane) and leaves the n1 row DFTs in LDS. Z never
 //    reaches HBM.
 //  * Output: for each k0 the 64 lanes store QW full n1*8-byte rows of
-//    consecutive windows, i.e. whole 128-byte lines, with non-temporal
-//    stores; the output is the only large HBM stream.
+//    consecutive windows (KG adjacent k0 rows for a split stream), i.e.
+//    whole 128-byte lines from n1 KG >= 16 on, with non-temporal stores
+//    (plain stores below that); the output is the only large HBM stream.
 //  * The first n0-1 rows of a slab only prime the rings (their windows belong
 //    to the previous slab); their outputs are not stored. Stores go through a
 //    buffer resource per output row whose range ends at the strip's last
@@ -267,13 +268,19 @@ __device__ __forceinline__ std::conditional_t<REAL, float, float2> load_buf(
   }
 }
 
-// Non-temporal 8-byte store at byte offset off of a buffer resource.
-__device__ __forceinline__ void store_buf_nt(__amdgpu_buffer_rsrc_t r, uint32_t off, float2 v) {
+// 8-byte store at byte offset off of a buffer resource, non-temporal by
+// default.
+template <bool NT = true>
+__device__ __forceinline__ void store_buf(__amdgpu_buffer_rsrc_t r, uint32_t off, float2 v) {
   constexpr int kNonTemporal = 2;
   u2v t;
   t.x = __float_as_uint(v.x);
   t.y = __float_as_uint(v.y);
-  __builtin_amdgcn_raw_buffer_store_b64(t, r, (int)off, 0, kNonTemporal);
+  __builtin_amdgcn_raw_buffer_store_b64(t, r, (int)off, 0, NT ? kNonTemporal : 0);
+}
+
+__device__ __forceinline__ void store_buf_nt(__amdgpu_buffer_rsrc_t r, uint32_t off, float2 v) {
+  store_buf<true>(r, off, v);
 }
 
 // Workgroup i runs on XCD i mod 8; give each XCD a contiguous block of tiles.
@@ -300,6 +307,13 @@ struct TreeCfg {
   static constexpr int ZS = N1W + 1;                        // padded stride of one window column in LDS
   static constexpr int ZROW = QW * ZS;                      // float2 per chunk row in LDS
   static constexpr int LDS_FLOAT2 = CR * ZROW;
+  // One store instruction writes, per window, KG adjacent k0 rows of n1
+  // complex64 values. Non-temporal stores are used when that covers whole
+  // 128-byte lines (KG n1 >= 16); narrower rows (n1 <= 8 unsplit, n1 <= 4
+  // split in two) take plain stores, so that L2 merges the k0 rows of a
+  // line before it is written back (non-temporal partial lines reached
+  // about 1 TB/s at 1024 x 1024 / 4 x 4).
+  static constexpr bool NT_STORES = KG * N1W >= 16;
   static_assert(KT == 1 || KT < N0W, "a split stream needs KG * WV < n0");
   static_assert((int64_t)CR * SWDFT_MAX_ROW * 8 <= (int64_t)kOutOfRange,
                 "one chunk of input rows must stay addressable with 32-bit offsets");
@@ -468,10 +482,10 @@ __device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float
       const auto out = buf_rsrc(ystrip + (row_store ? q0 : 0) * y_row_stride,
                                 row_store ? strip_bytes : 0u);
       if constexpr (N0W == 1) {
-        store_buf_nt(out, lane_off, z);
+        store_buf<C::NT_STORES>(out, lane_off, z);
       } else {
         column_levels<N0W, C::KT, st % C::RING>(z, ring, lanefac, lw, w0, [&](auto J, float2 v) {
-          store_buf_nt(out, lane_off + (C::KT * J) * N1W * (int)sizeof(float2), v);
+          store_buf<C::NT_STORES>(out, lane_off + (C::KT * J) * N1W * (int)sizeof(float2), v);
         });
       }
     });

@@ -346,3 +346,20 @@ def test_window64_limits_of_other_paths():
     assert lib.swdft2d_stream_create(ctypes.byref(s), 100, 8, 64, _lib.SWDFT_R32) == S["SWDFT_E_WINDOW"]
     assert lib.swdft2d_stream_create(ctypes.byref(s), 100, 32, 32, _lib.SWDFT_R32) == 0
     assert lib.swdft2d_stream_destroy(s) == 0
+
+
+@pytest.mark.parametrize("N,n,slab,slabs", [
+    (100, 16, 16, 6),     # 22 strips: one-chunk slabs rather than 44 long ones
+    (100, 32, 64, 2),     # split streams: 64-row chunks
+    (1024, 16, 1024, 1),  # one workgroup per CU walking whole columns
+])
+def test_tree_slab_rule(N, n, slab, slabs):
+    """Small images take one-chunk slabs when longer slabs would leave fewer
+    tiles than compute units (256 assumed without a device)."""
+    st, h = make_plan(N, N, n, n)
+    assert st == 0
+    buf = ctypes.create_string_buffer(512)
+    assert lib.swdft2d_describe(h, buf, 512) == 0
+    d = buf.value.decode()
+    assert f" slab={slab} " in d and f" slabs={slabs} " in d, d
+    lib.swdft2d_destroy(h)
