@@ -3,7 +3,8 @@
 Each pin takes an ``oracle.Oracle`` and raises AssertionError when the oracle
 disagrees with:
   * an independent formulation (the factorised matrix form F0 X F1^T of
-    Eq. (3)-(4), built with numpy; numpy.fft.fft2 on each window),
+    Eq. (3)-(4), built with numpy; numpy.fft.fft2 on each window, also for
+    windows of 3, 6, 9, 12 and 24),
   * exact Gaussian-integer brute force for n_i <= 4 (all twiddles are
     powers of -i there, so every sum is exact),
   * closed forms (impulse, constant, on-bin exponential and cosine),
@@ -61,6 +62,33 @@ def pin_fft2(orc):
             ref = np.fft.fft2(win, axes=(-2, -1))
             assert y.shape == (P0, P1, n0, n1)
             assert _rel(y, ref) < 1e-13, (N0, N1, n0, n1, cplx)
+
+
+def pin_mixed_radix(orc):
+    """Windows that are not powers of two (the radix-3 and mixed 2/3 trees of
+    Sec. 6): each window equals numpy.fft.fft2 of that window, the twiddle of
+    a third of a turn is exp(-2 pi i / 3) (checked through an on-bin
+    exponential), and Parseval holds per window."""
+    rng = np.random.default_rng(14)
+    for (N0, N1, n0, n1) in [(9, 14, 3, 6), (20, 15, 12, 9), (30, 7, 24, 3), (13, 27, 6, 12)]:
+        x = rng.standard_normal((N0, N1)) + 1j * rng.standard_normal((N0, N1))
+        y = orc.swdft2d(x, n0, n1)
+        win = np.lib.stride_tricks.sliding_window_view(x, (n0, n1))
+        assert _rel(y, np.fft.fft2(win, axes=(-2, -1))) < 1e-13, (N0, N1, n0, n1)
+        energy = np.sum(np.abs(win) ** 2, axis=(-2, -1))
+        assert np.allclose(np.sum(np.abs(y) ** 2, axis=(-2, -1)), n0 * n1 * energy, rtol=1e-12)
+    # x = exp(2 pi i (k0 r / 3 + k1 c / 6)): every window is on bin (k0, k1) with
+    # value n0 n1 times the phase of its corner, all other bins zero
+    N0, N1, n0, n1, k0, k1 = 8, 11, 3, 6, 1, 5
+    r, c = np.meshgrid(np.arange(N0), np.arange(N1), indexing="ij")
+    x = np.exp(2j * np.pi * (k0 * r / n0 + k1 * c / n1))
+    y = orc.swdft2d(x, n0, n1)
+    P0, P1 = N0 - n0 + 1, N1 - n1 + 1
+    q0, q1 = np.meshgrid(np.arange(P0), np.arange(P1), indexing="ij")
+    corner = np.exp(2j * np.pi * (k0 * q0 / n0 + k1 * q1 / n1))
+    assert np.allclose(y[:, :, k0, k1], n0 * n1 * corner, atol=1e-12)
+    y[:, :, k0, k1] = 0
+    assert np.max(np.abs(y)) < 1e-12
 
 
 def pin_whole_array(orc):
@@ -383,7 +411,7 @@ def pin3d_parseval_ortho(orc):
 PINS_3D = [pin3d_fftn, pin3d_separable, pin3d_exact_small, pin3d_shift_axis2,
            pin3d_parseval_ortho]
 
-ALL_PINS = [pin_matrix_form, pin_fft2, pin_whole_array, pin_exact_small, pin_impulse,
+ALL_PINS = [pin_matrix_form, pin_fft2, pin_mixed_radix, pin_whole_array, pin_exact_small, pin_impulse,
             pin_constant, pin_onbin_exponential, pin_onbin_cosine, pin_parseval,
             pin_shift_theorem, pin_linearity_and_sampling, pin_adjoint_dot,
             pin_adjoint_sampled, pin_quadratic_fd] + PINS_3D
