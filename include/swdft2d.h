@@ -2,8 +2,9 @@
  * swdft2d.h - C ABI of the MI355X (gfx950) 2D Tree Sliding-Window DFT library.
  *
  * Problem (Sec. 4.1, Eq. (2)): for an N0 x N1 array x and radix-2 windows
- * n0 = 2^m0, n1 = 2^m1 (n_i <= N_i, non-square allowed), compute for every
- * window position the 2D DFT of that n0 x n1 window:
+ * n0 = 2^m0, n1 = 2^m1 (n_i <= N_i, non-square allowed), or mixed-radix
+ * windows whose sides are 2^a 3^b (Sec. 6; see swdft2d_plan), compute for
+ * every window position the 2D DFT of that n0 x n1 window:
  *
  *   y[b][q0][q1][k0][k1] = s * sum_{j0<n0} sum_{j1<n1} x[b][q0+j0][q1+j1]
  *                          * exp(-2 pi i (j0 k0 / n0 + j1 k1 / n1))
@@ -20,6 +21,8 @@
  *            column levels (Eq. (6)) swept over the whole grid so every
  *            sub-DFT shared by overlapping windows is computed once per tile.
  *            FP32 arithmetic, twiddles generated in FP64 and rounded once.
+ *            Sides with a factor 3 run ternary levels (3-point butterflies)
+ *            after the binary ones.
  *   DENSE_BF16X2 - each window as F_n0 X F_n1^T on the matrix cores, BF16
  *            hi/lo split products accumulated in FP32 (n0, n1 in {8,16,32};
  *            normwise relative error about 5e-6 instead of the tree's 2e-7).
@@ -87,7 +90,8 @@ typedef enum {
 typedef int swdft_status_t;
 #define SWDFT_OK 0
 #define SWDFT_E_ARG 1         /* null pointer, size <= 0, unknown enum value */
-#define SWDFT_E_NOT_POW2 2    /* n0 or n1 is not a power of two (radix-2, Sec. 4.1) */
+#define SWDFT_E_NOT_POW2 2    /* window shape is neither radix-2 (Sec. 4.1) nor one of
+                                 the mixed-radix shapes of swdft2d_plan */
 #define SWDFT_E_WINDOW 3      /* n_i > N_i, or n_i above SWDFT_MAX_WINDOW */
 #define SWDFT_E_DTYPE 4       /* dtype / algorithm combination not supported */
 #define SWDFT_E_OVERFLOW 5    /* element or byte count does not fit in int64 */
@@ -107,7 +111,10 @@ typedef struct swdft2d_plan_s* swdft2d_plan_t;
 
 /* Create a plan for `batch` images of N0 x N1 with n0 x n1 windows.
  * Checks, in this order: out != NULL (E_ARG); N0, N1, n0, n1, batch >= 1 and
- * dtype known (E_ARG); n0, n1 powers of two (E_NOT_POW2); n_i <= N_i and
+ * dtype known (E_ARG); n0, n1 powers of two, or both from {3, 4, 6, 8, 9, 12,
+ * 16, 24} with at least one of them in {3, 6, 9, 12, 24} (E_NOT_POW2: the
+ * mixed-radix tree; such plans run TREE or DIRECT_F64 forward only, and
+ * swdft2d_backward, SWFFT and DENSE_BF16X2 return E_WINDOW); n_i <= N_i and
  * n_i <= SWDFT_MAX_WINDOW (E_WINDOW); batch*P0*P1*n0*n1 and its byte count fit
  * in int64, and N1 <= SWDFT_MAX_ROW (E_OVERFLOW). Builds the twiddle vectors
  * Omega^0, Omega^1 of Sec. 4.2 in FP64 (exact at quarter turns, Omega[m + n/2] = -Omega[m]) and
@@ -121,7 +128,8 @@ swdft_status_t swdft2d_set_norm(swdft2d_plan_t plan, swdft_norm_t norm);
 /* Select the algorithm. E_DTYPE if it cannot serve the plan's dtype (TREE,
  * DENSE_BF16X2 and SWFFT serve R32/C32; DIRECT_F64 serves R64/C64, whose callers widen
  * FP32 data to FP64 exactly beforehand); E_WINDOW if DENSE_BF16X2 is asked for
- * a window outside {8,16,32} x {8,16,32}. */
+ * a window outside {8,16,32} x {8,16,32}, or SWFFT for a window that is not
+ * radix-2. */
 swdft_status_t swdft2d_set_algo(swdft2d_plan_t plan, swdft_algo_t algo);
 
 /* Forward transform: x (layout above) -> y. Enqueued on `stream`.
@@ -136,8 +144,8 @@ swdft_status_t swdft2d_exec(swdft2d_plan_t plan, const void* x, void* y, hipStre
  * respect to x when dy = dL/dRe(y) + i dL/dIm(y). Computed with the levels of
  * Eq. (5)-(6) transposed and run in reverse (gather form: deterministic, no
  * atomics). Supported for R32/C32 plans with TREE (or AUTO); E_DTYPE
- * otherwise. E_WINDOW for n_i above SWDFT_MAX_WINDOW_ADJ (checked first, after
- * the plan itself). Errors as for exec. Allocates the plan's workspace (partial sums
+ * otherwise. E_WINDOW for n_i above SWDFT_MAX_WINDOW_ADJ or a window that is
+ * not radix-2 (checked first, after the plan itself). Errors as for exec. Allocates the plan's workspace (partial sums
  * of (64/n1 + n1 - 1) x-columns per strip of 64/n1 window columns, about
  * (1 + n1^2/64) times the size of dx) on first use, or when called on another
  * device, with hipMalloc (E_NOMEM on failure); later calls reuse it. */

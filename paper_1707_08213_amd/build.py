@@ -20,6 +20,7 @@ SOURCES = ["abi.hip", "abi3d.hip", "abi_stream.hip", "tree3d_fwd.hip", "tree_str
            "batched_host.hip", "tune.hip",
            "tree_config.hip", "tree_fwd.hip",
            "write_probe.hip", "tree_adj.hip", "direct_f64.hip", "swfft_r.hip", "swfft_c.hip",
+           "tree_mixed.hip", "tree_mixed_pow2_r.hip", "tree_mixed_pow2_c.hip",
            "dense_mfma.hip",
            "dense_mfma_r.hip", "dense_mfma_c.hip", "batched.hip", "batched_tree_r.hip",
            "batched_tree_c.hip", "batched_dense_r.hip", "batched_dense_c.hip"] + [
@@ -28,7 +29,8 @@ SOURCES = ["abi.hip", "abi3d.hip", "abi_stream.hip", "tree3d_fwd.hip", "tree_str
     f"tree_fwd_n{n0}_{t}_{n1}.hip" for n0 in (16, 32) for t in ("r", "c") for n1 in (16, 32, 64)] + [
     f"tree_fwd_n64_{t}_{n1}.hip" for t in ("r", "c") for n1 in (16, 32, 64)] + [
     f"tree3d_fwd_n{n0}_{t}.hip" for n0 in (2, 4, 8, 16) for t in ("r", "c")] + [
-    f"tree_stream_n{n0}_{t}.hip" for n0 in (1, 2, 4, 8, 16, 32) for t in ("r", "c")]
+    f"tree_stream_n{n0}_{t}.hip" for n0 in (1, 2, 4, 8, 16, 32) for t in ("r", "c")] + [
+    f"tree_mixed_n{n0}_{t}.hip" for n0 in (3, 6, 9, 12, 24) for t in ("r", "c")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -74,16 +74,17 @@ int64_t x_elem_bytes(swdft_dtype_t d) {
 }
 int64_t y_elem_bytes(swdft_dtype_t d) { return f64_dtype(d) ? 16 : 8; }
 
-// Omega[m] = exp(-2 pi i m / n), m < n, in FP64. The first half is evaluated
-// with cos/sin except at the exact points m = 0 (1) and m = n/4 (-i); the
-// second half is the exact negation Omega[m + n/2] = -Omega[m].
+// Omega[m] = exp(-2 pi i m / n), m < n, in FP64. For even n the first half
+// is evaluated with cos/sin except at the exact points m = 0 (1) and m = n/4
+// (-i), and the second half is the exact negation Omega[m + n/2] = -Omega[m];
+// odd n (the mixed-radix sides 3 and 9) are evaluated directly for every m.
 void make_twiddles(int n, double2* w) {
   const double two_pi = 6.283185307179586476925286766559;
   if (n == 1) {
     w[0] = make_double2(1.0, 0.0);
     return;
   }
-  const int half = n / 2;
+  const int half = n % 2 == 0 ? n / 2 : n;
   for (int m = 0; m < half; ++m) {
     if (m == 0) {
       w[m] = make_double2(1.0, 0.0);
@@ -294,8 +295,9 @@ swdft_status_t swdft2d_plan(swdft2d_plan_t* out, int64_t N0, int64_t N1, int32_t
                 (long long)N0, (long long)N1, n0, n1, (long long)batch);
   if ((int)dtype < (int)SWDFT_R32 || (int)dtype > (int)SWDFT_C64)
     return fail(SWDFT_E_ARG, "unknown dtype %d", (int)dtype);
-  if (!is_pow2(n0) || !is_pow2(n1))
-    return fail(SWDFT_E_NOT_POW2, "window %d x %d is not radix-2", n0, n1);
+  if ((!is_pow2(n0) || !is_pow2(n1)) && !swdft::tree_mixed_supported(n0, n1))
+    return fail(SWDFT_E_NOT_POW2, "window %d x %d: sides must be powers of two, or from "
+                "{3, 6, 9, 12, 24} paired with each other or with {4, 8, 16}", n0, n1);
   if (n0 > N0 || n1 > N1)
     return fail(SWDFT_E_WINDOW, "window %d x %d larger than array %lld x %lld", n0, n1,
                 (long long)N0, (long long)N1);
@@ -363,6 +365,9 @@ swdft_status_t swdft2d_set_algo(swdft2d_plan_t plan, swdft_algo_t algo) {
       if (f64_dtype(plan->dtype))
         return fail(SWDFT_E_DTYPE, "algorithm %d computes in FP32 and needs an R32/C32 plan",
                     (int)algo);
+      if (algo == SWDFT_ALGO_SWFFT && mixed_window(plan))
+        return fail(SWDFT_E_WINDOW, "the per-window FFT is radix-2; window %d x %d is not",
+                    plan->n0, plan->n1);
       if (algo == SWDFT_ALGO_DENSE_BF16X2 && !swdft::dense_supported(plan->n0, plan->n1))
         return fail(SWDFT_E_WINDOW, "the dense BF16x2 algorithm supports n0, n1 in {8, 16, 32}, "
                     "not %d x %d", plan->n0, plan->n1);
@@ -391,8 +396,16 @@ swdft_status_t swdft2d_exec(swdft2d_plan_t plan, const void* x, void* y, hipStre
   hipError_t e = hipSuccess;
   switch (resolve_algo(p)) {
     case SWDFT_ALGO_TREE:
-      e = swdft::launch_tree_fwd(p->n0, p->n1, real_dtype(p->dtype), x,
-                                 static_cast<float2*>(y), tree_geom(p), p->tw32, stream);
+      if (mixed_window(p)) {
+        e = real_dtype(p->dtype)
+                ? swdft::launch_tree_mixed_r(p->n0, p->n1, x, static_cast<float2*>(y),
+                                             tree_geom(p), p->tw32, stream)
+                : swdft::launch_tree_mixed_c(p->n0, p->n1, x, static_cast<float2*>(y),
+                                             tree_geom(p), p->tw32, stream);
+      } else {
+        e = swdft::launch_tree_fwd(p->n0, p->n1, real_dtype(p->dtype), x,
+                                   static_cast<float2*>(y), tree_geom(p), p->tw32, stream);
+      }
       break;
     case SWDFT_ALGO_DENSE_BF16X2:
       e = swdft::launch_dense_fwd(p->n0, p->n1, real_dtype(p->dtype), x, static_cast<float2*>(y),
@@ -416,8 +429,8 @@ swdft_status_t swdft2d_exec(swdft2d_plan_t plan, const void* x, void* y, hipStre
 swdft_status_t swdft2d_backward(swdft2d_plan_t plan, const void* dy, void* dx, hipStream_t stream) {
   if (!is_live(plan)) return fail(SWDFT_E_PLAN, "null or destroyed plan");
   if (plan->kind == 1) return fail(SWDFT_E_PLAN, "backward is not available for batched plans");
-  if (plan->n0 > SWDFT_MAX_WINDOW_ADJ || plan->n1 > SWDFT_MAX_WINDOW_ADJ)
-    return fail(SWDFT_E_WINDOW, "backward supports windows up to %d, not %d x %d",
+  if (plan->n0 > SWDFT_MAX_WINDOW_ADJ || plan->n1 > SWDFT_MAX_WINDOW_ADJ || mixed_window(plan))
+    return fail(SWDFT_E_WINDOW, "backward supports power-of-two windows up to %d, not %d x %d",
                 SWDFT_MAX_WINDOW_ADJ, plan->n0, plan->n1);
   const swdft2d_plan_s* p = plan;
   const int64_t xb = p->batch * p->N0 * p->N1 * x_elem_bytes(p->dtype);
@@ -495,12 +508,12 @@ swdft_status_t swdft2d_describe(swdft2d_plan_t plan, char* buf, int32_t len) {
     const swdft::TreeGeom g = tree_geom(p);
     snprintf(buf, (size_t)len,
              "algo=tree n=%dx%d N=%lldx%lld batch=%lld kg=%d cols_per_wave=%d rows_per_chunk=%d "
-             "slab=%d strips=%d slabs=%d waves=%lld waves_per_strip=%d groups_per_cu=%d order=%s",
+             "slab=%d strips=%d slabs=%d waves=%lld waves_per_strip=%d groups_per_cu=%d order=%s "
+             "radix=%s",
              p->n0, p->n1, (long long)p->N0, (long long)p->N1, (long long)p->batch, g.kg,
-             swdft::tree_fwd_columns_per_wave(p->n0, p->n1, g.kg),
-             swdft::tree_fwd_rows_per_chunk(p->n0, p->n1, g.kg, g.wv), g.S, g.nstrips, g.nslabs,
-             (long long)g.nstrips * g.nslabs * p->batch * g.wv, g.wv, g.wpc,
-             g.order ? "dispatch" : "xcd");
+             swdft::tree_fwd_columns_per_wave(p->n0, p->n1, g.kg), tree_chunk_rows(p, g.kg, g.wv),
+             g.S, g.nstrips, g.nslabs, (long long)g.nstrips * g.nslabs * p->batch * g.wv, g.wv,
+             g.wpc, g.order ? "dispatch" : "xcd", mixed_window(p) ? "2,3" : "2");
   } else if (a == SWDFT_ALGO_DENSE_BF16X2) {
     const swdft::DenseGeom g = dense_geom(p);
     snprintf(buf, (size_t)len,

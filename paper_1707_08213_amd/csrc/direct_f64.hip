@@ -75,11 +75,15 @@ __global__ __launch_bounds__(kDirectThreads) void direct_f64_kernel(const void* 
     const int k0 = (t / n1) % n0;
     const int k1 = t % n1;
     double ar = 0.0, ai = 0.0;
+    int e0 = 0;  // (j0 k0) mod n0, stepped (any n, not only powers of two)
     for (int j0 = 0; j0 < n0; ++j0) {
       const double2* xrow = xs + j0 * cols + w;
       double sr = 0.0, si = 0.0;
+      int e1 = 0;  // (j1 k1) mod n1
       for (int j1 = 0; j1 < n1; ++j1) {
-        const double2 tw1 = w1s[(j1 * k1) & (n1 - 1)];
+        const double2 tw1 = w1s[e1];
+        e1 += k1;
+        if (e1 >= n1) e1 -= n1;
         const double2 v = xrow[j1];
         if constexpr (REAL) {
           sr += v.x * tw1.x;
@@ -89,7 +93,9 @@ __global__ __launch_bounds__(kDirectThreads) void direct_f64_kernel(const void* 
           si += v.x * tw1.y + v.y * tw1.x;
         }
       }
-      const double2 tw0 = w0s[(j0 * k0) & (n0 - 1)];
+      const double2 tw0 = w0s[e0];
+      e0 += k0;
+      if (e0 >= n0) e0 -= n0;
       ar += tw0.x * sr - tw0.y * si;
       ai += tw0.x * si + tw0.y * sr;
     }

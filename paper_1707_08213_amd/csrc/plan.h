@@ -80,7 +80,20 @@ struct swdft2d_plan_s {
 };
 
 namespace swdft {
+
+// Mixed-radix (2 and 3) tree kernels (tree_mixed.hip): window shapes they
+// serve (at least one side not a power of two), rows per chunk, launchers.
+bool tree_mixed_supported(int n0, int n1);
+int tree_mixed_rows_per_chunk(int n0, int n1);
+hipError_t launch_tree_mixed_r(int n0, int n1, const void* x, float2* y, const TreeGeom& g,
+                               const TwiddlesF32& tw, hipStream_t s);
+hipError_t launch_tree_mixed_c(int n0, int n1, const void* x, float2* y, const TreeGeom& g,
+                               const TwiddlesF32& tw, hipStream_t s);
+
 namespace host {
+
+// The plan's window has a side that is not a power of two (mixed-radix tree).
+bool mixed_window(const swdft2d_plan_s* p);
 
 swdft_status_t fail(swdft_status_t st, const char* fmt, ...);
 swdft_status_t device_fail(hipError_t e, const char* what);
@@ -98,6 +111,8 @@ void make_twiddles_f32(int n, float2* w);
 float norm_scale(swdft_norm_t norm, int n0, int n1);
 swdft_algo_t resolve_algo(const swdft2d_plan_s* p);
 TreeGeom tree_geom(const swdft2d_plan_s* p);
+// Rows per chunk of the plan's tree kernel (radix-2 or mixed-radix).
+int tree_chunk_rows(const swdft2d_plan_s* p, int kg, int wv);
 DenseGeom dense_geom(const swdft2d_plan_s* p);
 bool ranges_overlap(const void* a, int64_t abytes, const void* b, int64_t bbytes);
 

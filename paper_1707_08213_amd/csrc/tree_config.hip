@@ -43,6 +43,7 @@ int cu_count() {
 namespace {
 
 int32_t tree_kg(const swdft2d_plan_s* p) {
+  if (mixed_window(p)) return 1;  // the mixed-radix kernels keep streams whole
   int kg = p->tree_kg > 0 ? p->tree_kg : env_int("SWDFT_TREE_KG", 0);
   if (kg <= 0 || !swdft::tree_fwd_kg_supported(p->n0, p->n1, kg))
     kg = swdft::tree_fwd_default_kg(p->n0, p->n1);
@@ -82,6 +83,7 @@ bool capped_by_default(int n0, int n1, int kg) {
 bool two_waves_by_default(int n0, int n1, int kg) { return n0 >= 16 && n1 == 8 && kg == 2; }
 
 TreeCap tree_cap(const swdft2d_plan_s* p, int kg) {
+  if (mixed_window(p)) return TreeCap{};
   const int64_t columns =
       ceil_div(p->P1, swdft::tree_fwd_columns_per_wave(p->n0, p->n1, kg)) * p->batch;
   const int64_t ncu = cu_count() > 0 ? cu_count() : 256;
@@ -105,6 +107,7 @@ TreeCap tree_cap(const swdft2d_plan_s* p, int kg) {
 // to 6.7-6.9 TB/s, 2048x512 / 32x8 from 5.4 to 5.55); one otherwise (for
 // unsplit n0 = 16 streams a second wave lowered the write rate by 11%).
 int32_t tree_wv(const swdft2d_plan_s* p, int kg, int wpc) {
+  if (mixed_window(p)) return 1;
   int wv = p->tree_wv > 0 ? p->tree_wv : env_int("SWDFT_TREE_WV", 0);
   if (wv <= 0) wv = (wpc == 1 && two_waves_by_default(p->n0, p->n1, kg)) ? 2 : 1;
   if (!swdft::tree_fwd_wv_supported(p->n0, kg, wv)) wv = 1;
@@ -117,7 +120,7 @@ int32_t tree_wv(const swdft2d_plan_s* p, int kg, int wpc) {
 // with slabs long enough that the n0-1 priming rows at the top of each stay a
 // small fraction of the work.
 int32_t tree_slab(const swdft2d_plan_s* p, int kg, int wv, const TreeCap& cap) {
-  const int cr = swdft::tree_fwd_rows_per_chunk(p->n0, p->n1, kg, wv);
+  const int cr = tree_chunk_rows(p, kg, wv);
   const int64_t nstrips = ceil_div(p->P1, swdft::tree_fwd_columns_per_wave(p->n0, p->n1, kg));
   int64_t S = p->tree_slab > 0 ? p->tree_slab : env_int("SWDFT_TREE_SLAB", 0);
   if (S <= 0) {
@@ -141,6 +144,13 @@ int32_t tree_slab(const swdft2d_plan_s* p, int kg, int wv, const TreeCap& cap) {
 }
 
 }  // namespace
+
+bool mixed_window(const swdft2d_plan_s* p) { return !is_pow2(p->n0) || !is_pow2(p->n1); }
+
+int tree_chunk_rows(const swdft2d_plan_s* p, int kg, int wv) {
+  return mixed_window(p) ? swdft::tree_mixed_rows_per_chunk(p->n0, p->n1)
+                         : swdft::tree_fwd_rows_per_chunk(p->n0, p->n1, kg, wv);
+}
 
 swdft::TreeGeom tree_geom(const swdft2d_plan_s* p) {
   swdft::TreeGeom g{};

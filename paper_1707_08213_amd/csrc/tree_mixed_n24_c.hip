@@ -1,0 +1,10 @@
+// Mixed-radix forward tree kernels with n0 = 24, complex input (every
+// n1); see tree_mixed_kernel.h.
+#include "tree_mixed_kernel.h"
+
+namespace swdft {
+hipError_t launch_tree_mixed_n0_24_c(int n1, const void* x, float2* y, const TreeGeom& g,
+                                     const TwiddlesF32& tw, hipStream_t s) {
+  return mixed::launch_n0<24, false>(n1, x, y, g, tw, s);
+}
+}  // namespace swdft

@@ -389,7 +389,8 @@ extern "C" swdft_status_t swdft2d_tune(swdft2d_plan_t plan, const void* x, void*
   if (!is_live(plan)) return fail(SWDFT_E_PLAN, "null or destroyed plan");
   if (!x || !y) return fail(SWDFT_E_ARG, "x or y is null");
   if (plan->kind == 0 && f64_dtype(plan->dtype)) return SWDFT_OK;  // one algorithm: nothing to tune
-  if (plan->kind == 0 && plan->algo == SWDFT_ALGO_SWFFT) return SWDFT_OK;  // one fixed shape
+  if (plan->kind == 0 && (plan->algo == SWDFT_ALGO_SWFFT || mixed_window(plan)))
+    return SWDFT_OK;  // one fixed launch shape
   const swdft_status_t st =
       plan->kind == 1 ? tune_batched(plan, x, y, stream) : tune_single(plan, x, y, stream);
   if (st != SWDFT_OK) return st;

@@ -46,8 +46,8 @@ def make_plan(N0, N1, n0, n1, dtype=_lib.SWDFT_R32, batch=1):
     ((64, 64, 4, 4, 0, 0), "SWDFT_E_ARG"),
     ((64, 64, 0, 4, 0, 1), "SWDFT_E_ARG"),
     ((64, 64, 4, 4, 7, 1), "SWDFT_E_ARG"),
-    ((64, 64, 12, 4, 0, 1), "SWDFT_E_NOT_POW2"),
-    ((64, 64, 4, 3, 0, 1), "SWDFT_E_NOT_POW2"),
+    ((64, 64, 10, 4, 0, 1), "SWDFT_E_NOT_POW2"),
+    ((64, 64, 4, 5, 0, 1), "SWDFT_E_NOT_POW2"),
     ((8, 64, 16, 4, 0, 1), "SWDFT_E_WINDOW"),
     ((128, 128, 64, 4, 0, 1), "SWDFT_OK"),
     ((100, 100, 64, 64, 0, 1), "SWDFT_OK"),
@@ -363,3 +363,36 @@ def test_tree_slab_rule(N, n, slab, slabs):
     d = buf.value.decode()
     assert f" slab={slab} " in d and f" slabs={slabs} " in d, d
     lib.swdft2d_destroy(h)
+
+
+@pytest.mark.parametrize("n0,n1,status", [
+    (12, 9, "SWDFT_OK"), (24, 24, "SWDFT_OK"), (3, 16, "SWDFT_OK"), (8, 6, "SWDFT_OK"),
+    (5, 4, "SWDFT_E_NOT_POW2"), (18, 3, "SWDFT_E_NOT_POW2"), (27, 3, "SWDFT_E_NOT_POW2"),
+    (3, 2, "SWDFT_E_NOT_POW2"), (32, 3, "SWDFT_E_NOT_POW2"), (12, 64, "SWDFT_E_NOT_POW2")])
+def test_mixed_radix_windows(n0, n1, status):
+    """Sides from {3, 6, 9, 12, 24} pair with each other and with {4, 8, 16}."""
+    st, h = make_plan(100, 100, n0, n1)
+    assert st == S[status], (n0, n1, st)
+    if st == 0:
+        lib.swdft2d_destroy(h)
+
+
+def test_mixed_radix_plan_rules():
+    st, h = make_plan(200, 100, 24, 24)
+    assert st == 0
+    buf = ctypes.create_string_buffer(512)
+    assert lib.swdft2d_describe(h, buf, 512) == 0
+    d = buf.value.decode()
+    # two 24-wide windows per wave (48 lanes), 32 rows per pass, ring period 12
+    assert "radix=2,3" in d and " kg=1 " in d and " cols_per_wave=2 " in d, d
+    assert " rows_per_chunk=96 " in d, d
+    assert lib.swdft2d_set_algo(h, _lib.SWDFT_ALGO_SWFFT) == S["SWDFT_E_WINDOW"]
+    assert lib.swdft2d_set_algo(h, _lib.SWDFT_ALGO_DENSE_BF16X2) == S["SWDFT_E_WINDOW"]
+    assert lib.swdft2d_backward(h, None, None, None) == S["SWDFT_E_WINDOW"]
+    lib.swdft2d_destroy(h)
+    st, h = make_plan(100, 100, 12, 9, _lib.SWDFT_C64)
+    assert st == 0 and lib.swdft2d_set_algo(h, _lib.SWDFT_ALGO_DIRECT_F64) == 0
+    lib.swdft2d_destroy(h)
+    s = ctypes.c_void_p()
+    assert lib.swdft2d_stream_create(ctypes.byref(s), 100, 12, 8, _lib.SWDFT_R32) == \
+        S["SWDFT_E_NOT_POW2"]
