@@ -18,6 +18,8 @@ Other workloads (one JSON line each, same fields where they apply):
              L = sum w |A|^2 (band mask w); the adjoint kernel is read-bound.
   uneven64 - 64 real FP32 images of uneven sizes and window shapes in one
              batched graph launch, after autotuning.
+  mixed1024 - 1024 x 1024 real FP32, 12 x 12 windows through the mixed-radix
+             (2 and 3) tree; 9 x 9, 24 x 24 and 12 x 16 as extra lines.
 
 ``--fig4`` runs the speed comparison of Fig. 4 instead (a markdown table, no
 JSON line): square windows n = 4..64 over a 100 x 100 real array, and over a
@@ -391,6 +393,75 @@ def run_cplx2048(args, swd, dev) -> dict:
     return out
 
 
+def run_mixed1024(args, swd, dev) -> dict:
+    """Mixed-radix tree: 1024 x 1024 real FP32, 12 x 12 windows (levels of
+    radix 2, 2, 3 per side), the FP64 direct form on the same GPU; 9 x 9,
+    24 x 24 and 12 x 16 windows on the same image as extra lines."""
+    import numpy as np
+    import torch
+
+    import workloads
+    wl = workloads.mixed1024()
+    x_np = wl["x"]
+    N0, N1 = x_np.shape
+    n0, n1 = wl["n0"], wl["n1"]
+    P0, P1 = N0 - n0 + 1, N1 - n1 + 1
+    x = torch.from_numpy(x_np).to(dev).unsqueeze(0)
+    stream = torch.cuda.current_stream(dev)
+    plan = swd.Plan(N0, N1, n0, n1, torch.float32, batch=1)
+    coeffs = plan.output_elems()
+    alg_bytes = plan.output_bytes() + x.numel() * 4
+    log(plan.describe())
+    y, avg_ms, step_s = forward_leg(plan, x, args, stream)
+    rf = roofline(alg_bytes, avg_ms, f"tree_mixed_kernel<{n0},{n1},real>")
+    log(f"mixed tree {n0}x{n1}: {avg_ms * 1e3:.1f} us/launch, {rf['achieved']:.0f} GB/s")
+    q0, q1 = workloads.window_sample(P0, P1, 4096, 2008)
+    got = sampled(y[0], q0, q1)
+    del y
+    torch.cuda.empty_cache()
+    comp = None
+    if not args.no_comparator:
+        pd = swd.Plan(N0, N1, n0, n1, torch.float64, batch=1, algo="direct_f64")
+        xd = x.double()
+        yd = torch.empty(pd.out_shape, dtype=pd.out_dtype, device=dev)
+        pd.forward(xd, out=yd)
+        torch.cuda.synchronize()
+        steps = max(3, min(args.steps, 20))
+        d_ms, d_wall, _ = time_launches(lambda: pd.forward(xd, out=yd), steps, stream)
+        comp = {"algo": "direct_f64", "value": coeffs / (d_wall / steps), "unit": "coeffs/s",
+                "avg_launch_ms": d_ms, "dtype": "f64", "tree_speedup": d_ms / avg_ms}
+        log(f"direct_f64 {n0}x{n1}: {d_ms:.2f} ms/launch")
+        del yd
+        torch.cuda.empty_cache()
+    extra = []
+    for (m0, m1) in ((9, 9), (24, 24), (12, 16)):
+        pe = swd.Plan(N0, N1, m0, m1, torch.float32, batch=1)
+        _, e_ms, _ = forward_leg(pe, x, args, stream)
+        eb = pe.output_bytes() + x.numel() * 4
+        extra.append({"n0": m0, "n1": m1, "avg_launch_us": e_ms * 1e3,
+                      "coeffs_per_s": pe.output_elems() / (e_ms * 1e-3),
+                      "achieved_GBps": eb / (e_ms * 1e-3) / 1e9,
+                      "frac": eb / (e_ms * 1e-3) / 1e9 / PEAK_HBM_GBS})
+        log(f"mixed tree {m0}x{m1}: {e_ms * 1e3:.1f} us/launch")
+        torch.cuda.empty_cache()
+    cpu, err = None, None
+    if not args.no_cpu_baseline:
+        import oracle
+        orc = oracle.get()
+        xd = x_np.astype(np.float64)
+        err = rel(got, orc.swdft2d(xd, n0, n1, windows=(q0, q1)))
+        cpu = oracle_rate(orc, xd, n0, n1, P0, P1, args.cpu_seconds, 3008)
+    out = base_record(args, coeffs / step_s, step_s * 1e3, "f32", {
+        "workload": "mixed1024: one 1024x1024 real FP32 image, N(0,1), 12x12 windows "
+                    "(mixed-radix tree, levels of radix 2, 2, 3) -> 1013x1013x144 complex64 "
+                    "coefficients",
+        "N0": N0, "N1": N1, "n0": n0, "n1": n1, "batch": 1, "algo": "tree (mixed radix)",
+        "coeffs_per_step": coeffs})
+    out.update({"roofline": rf, "rel_err": err, "comparator": comp, "other_windows": extra,
+                "cpu_baseline": cpu})
+    return out
+
+
 def oracle_rate3(orc, x3d, n, P, seconds: float, seed: int):
     """Time the 3D oracle on a seeded window sample sized to about `seconds`."""
     import workloads
@@ -653,7 +724,7 @@ def run_uneven64(args, swd, dev) -> dict:
 
 WORKLOADS = {"sin1024": run_sin1024, "cplx2048": run_cplx2048, "grad256": run_grad256,
              "vol128": run_vol128, "stream1024": run_stream1024,
-             "uneven64": run_uneven64}
+             "uneven64": run_uneven64, "mixed1024": run_mixed1024}
 
 
 FIG4_WINDOWS = (4, 8, 16, 32, 64)

@@ -83,7 +83,6 @@ bool capped_by_default(int n0, int n1, int kg) {
 bool two_waves_by_default(int n0, int n1, int kg) { return n0 >= 16 && n1 == 8 && kg == 2; }
 
 TreeCap tree_cap(const swdft2d_plan_s* p, int kg) {
-  if (mixed_window(p)) return TreeCap{};
   const int64_t columns =
       ceil_div(p->P1, swdft::tree_fwd_columns_per_wave(p->n0, p->n1, kg)) * p->batch;
   const int64_t ncu = cu_count() > 0 ? cu_count() : 256;
@@ -91,9 +90,12 @@ TreeCap tree_cap(const swdft2d_plan_s* p, int kg) {
   c.wpc = p->tree_wpc >= 0 ? p->tree_wpc : env_int("SWDFT_TREE_WPC", -1);
   if (c.wpc < 0) {
     c.wpc = 0;
-    if (capped_by_default(p->n0, p->n1, kg)) {
-      const int64_t s = filling_slabs(columns, ncu);
-      if (s > 0) c = TreeCap{1, s};
+    if (mixed_window(p) ? p->n0 * p->n1 >= 144 : capped_by_default(p->n0, p->n1, kg)) {
+      // mixed-radix windows of 12 x 12 and up: two resident workgroups per CU
+      // (1024 x 1024: 12 x 12 259 -> 246 us, 24 x 24 1026 -> 914 us)
+      const int wpc = mixed_window(p) ? 2 : 1;
+      const int64_t s = filling_slabs(columns, ncu * wpc);
+      if (s > 0) c = TreeCap{wpc, s};
     }
     return c;
   }

@@ -32,7 +32,8 @@
 //    twiddle products and L_{u-1} butterflies of r_u points.
 //  * Output: plain stores except for n1 = 16, where a store covers whole
 //    128-byte lines of a window; inputs of the next chunk are loaded before
-//    the column phase of the current one.
+//    the column phase of the current one. Resident workgroups per CU may be
+//    capped and tiles then run in dispatch order, as for the radix-2 kernel.
 #pragma once
 
 #include "tree_fwd_kernel.h"
@@ -230,7 +231,7 @@ __global__ __launch_bounds__(64) void tree_mixed_kernel(const void* __restrict__
   using C = MixedCfg<N0W, N1W, REAL>;
   __shared__ float2 zl[C::LDS_FLOAT2];
   const TreeGeom g = uniform_copy(g_in);
-  int id = xcd_tile(blockIdx.x, gridDim.x);
+  int id = g.order ? (int)blockIdx.x : xcd_tile(blockIdx.x, gridDim.x);
   const int strip = id % g.nstrips;
   id /= g.nstrips;
   const int slab = id % g.nslabs;
@@ -354,8 +355,11 @@ hipError_t launch_one(const void* x, float2* y, const TreeGeom& g, const Twiddle
                       hipStream_t stream) {
   const int64_t nb = (int64_t)g.batch * g.nslabs * g.nstrips;
   if (nb < 1 || nb > 0x7fffffff) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((tree_mixed_kernel<N0W, N1W, REAL>), dim3((unsigned)nb), dim3(64), 0, stream,
-                     x, y, g, tw);
+  // optional cap on resident workgroups per CU, as for the radix-2 kernel
+  const unsigned pad = tree::occupancy_lds(
+      g.wpc, g.lds_cu, MixedCfg<N0W, N1W, REAL>::LDS_FLOAT2 * (unsigned)sizeof(float2));
+  hipLaunchKernelGGL((tree_mixed_kernel<N0W, N1W, REAL>), dim3((unsigned)nb), dim3(64), pad,
+                     stream, x, y, g, tw);
   return hipGetLastError();
 }
 

@@ -156,9 +156,11 @@ swdft_status_t tune_single(swdft2d_plan_s* p, const void* x, void* y, hipStream_
   if (allow_tree) {
     // slabs: the automatic choice for each cap, the whole column, and about
     // 256 to 4096 tiles; caps: none, one or two resident waves per CU
+    // the mixed-radix kernels run unsplit streams on one wave per strip
+    const bool mixed = mixed_window(p);
     for (int kg : {1, 2, 4, 8}) {
-      if (!tree_fwd_kg_supported(p->n0, p->n1, kg)) continue;
-      const int cr = tree_fwd_rows_per_chunk(p->n0, p->n1, kg);
+      if (!tree_fwd_kg_supported(p->n0, p->n1, kg) || (mixed && kg != 1)) continue;
+      const int cr = tree_chunk_rows(p, kg, 1);
       const int64_t columns =
           ceil_div(p->P1, tree_fwd_columns_per_wave(p->n0, p->n1, kg)) * p->batch;
       std::vector<int64_t> slabs = {p->P0};
@@ -174,7 +176,7 @@ swdft_status_t tune_single(swdft2d_plan_s* p, const void* x, void* y, hipStream_
         sl = std::min<int64_t>(sl, ceil_div(p->P0, cr) * cr);
         for (int wpc : {0, 1, 2}) {
           for (int wv : {1, 2}) {
-            if (!tree_fwd_wv_supported(p->n0, kg, wv)) continue;
+            if (!tree_fwd_wv_supported(p->n0, kg, wv) || (mixed && wv != 1)) continue;
             bool dup = false;
             for (auto& c : cands)
               dup |= (!c.dense && c.kg == kg && c.slab == sl && c.wpc == wpc && c.wv == wv);
@@ -389,8 +391,7 @@ extern "C" swdft_status_t swdft2d_tune(swdft2d_plan_t plan, const void* x, void*
   if (!is_live(plan)) return fail(SWDFT_E_PLAN, "null or destroyed plan");
   if (!x || !y) return fail(SWDFT_E_ARG, "x or y is null");
   if (plan->kind == 0 && f64_dtype(plan->dtype)) return SWDFT_OK;  // one algorithm: nothing to tune
-  if (plan->kind == 0 && (plan->algo == SWDFT_ALGO_SWFFT || mixed_window(plan)))
-    return SWDFT_OK;  // one fixed launch shape
+  if (plan->kind == 0 && plan->algo == SWDFT_ALGO_SWFFT) return SWDFT_OK;  // one fixed shape
   const swdft_status_t st =
       plan->kind == 1 ? tune_batched(plan, x, y, stream) : tune_single(plan, x, y, stream);
   if (st != SWDFT_OK) return st;

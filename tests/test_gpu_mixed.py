@@ -103,3 +103,24 @@ def test_mixed_tree_1024_sampled(swd, orc, n):
     torch.cuda.empty_cache()
     ref = orc.swdft2d(x.astype(np.float64), n, n, windows=(q0, q1))
     assert rel_err(got, ref) <= TOL
+
+
+def test_mixed_tree_tuned_and_capped(swd, orc, monkeypatch):
+    """The tuner's pick (slab and resident cap; streams stay whole) and an
+    explicit one-workgroup-per-CU cap both give the transform."""
+    x = workloads.normal_real((300, 260), seed=1500)
+    xt = torch.from_numpy(x).cuda().unsqueeze(0)
+    q0, q1 = workloads.window_sample(300 - 12 + 1, 260 - 12 + 1, 256, 1501)
+    ref = orc.swdft2d(x.astype(np.float64), 12, 12, windows=(q0, q1))
+    p = swd.Plan(300, 260, 12, 12)
+    p.tune(xt)
+    print(f"[case] tuned {p.describe()}", flush=True)
+    assert " kg=1 " in p.describe() and " waves_per_strip=1 " in p.describe()
+    y = p.forward(xt)[0]
+    got = y[torch.from_numpy(q0).cuda(), torch.from_numpy(q1).cuda()].cpu().numpy()
+    assert rel_err(got, ref) <= TOL
+    monkeypatch.setenv("SWDFT_TREE_WPC", "1")
+    y1, d = run(swd, x, 12, 12)
+    assert " groups_per_cu=1 " in d, d
+    got1 = y1[0][q0, q1]
+    assert rel_err(got1, ref) <= TOL

@@ -25,7 +25,7 @@ from __future__ import annotations
 import numpy as np
 
 WORKLOAD_SEEDS = {"small64": 1, "sin1024": 2, "cplx2048": 3, "uneven64": 4, "grad256": 5,
-                  "vol128": 6, "fig4": 7}
+                  "vol128": 6, "fig4": 7, "mixed1024": 8}
 
 UNEVEN_SIDES = (128, 256, 512, 1024)
 UNEVEN_WINDOWS = ((8, 8), (16, 16), (32, 32), (8, 32))
@@ -138,6 +138,12 @@ def sin1024(seed: int = WORKLOAD_SEEDS["sin1024"], N0: int = 1024, N1: int = 102
     noise = rng.standard_normal((N0, N1))
     planted, freqs = planted_cosines(N0, N1, n0, n1, 3, 5.0, rng)
     return dict(x=(noise + planted).astype(np.float32), n0=n0, n1=n1, planted=freqs)
+
+
+def mixed1024(seed: int = WORKLOAD_SEEDS["mixed1024"], N0: int = 1024, N1: int = 1024,
+              n0: int = 12, n1: int = 12):
+    """1024 x 1024 real N(0,1) image for the mixed-radix (2 and 3) tree."""
+    return dict(x=normal_real((N0, N1), seed), n0=n0, n1=n1)
 
 
 def cplx2048(seed: int = WORKLOAD_SEEDS["cplx2048"], N0: int = 2048, N1: int = 512,
