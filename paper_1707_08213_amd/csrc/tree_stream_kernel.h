@@ -9,8 +9,8 @@
 //
 // One wave owns QW = 64/n1 window columns (unsplit streams, KG = 1) and
 // processes the R rows of one call: the row levels (Eq. (5)) per position into
-// LDS, then the column levels with the rings loaded from, and at the end saved
-// to, the resident state. The state is kept in absolute row order: the nodes
+// LDS (inputs loaded a chunk ahead), then the column levels with the rings
+// loaded from, and at the end saved to, the resident state. The state is kept in absolute row order: the nodes
 // of tree p at level u-1 sit in tree slot (p mod s_u). The unrolled column phase
 // uses static ring slots (relative step mod s_u), so the load and the save
 // rotate by (first row mod s_u) through computed memory addresses. Steps past
@@ -45,7 +45,7 @@ __global__ __launch_bounds__(64) void tree_stream_kernel(const void* __restrict_
   const int64_t q0_first = max((int64_t)0, p_start - (N0W - 1));
 
   using XT = std::conditional_t<REAL, float, float2>;
-  const XT* x = reinterpret_cast<const XT*>(xv);
+  const XT* x = reinterpret_cast<const XT*>(xv);  // the call's first row
 
   // row-phase roles: lane (r, c)
   const int rp_r = lane / C::QW;
@@ -86,25 +86,41 @@ __global__ __launch_bounds__(64) void tree_stream_kernel(const void* __restrict_
     });
   });
 
-  for (int c = 0; c < nchunks; ++c) {
-    const int64_t rel0 = (int64_t)c * C::CR;  // relative index of the chunk's first row
-    // ---- row phase: CR rows x QW window columns of Z into LDS
-    sfor<0, C::CR / C::R>([&](auto PS) {
+  // Inputs of one chunk (rows rel_c + ps * R + r of the call) through a buffer
+  // resource over the call's rows: rows past the call and columns past the
+  // image edge read zero (Sec. 4.7). Loaded a chunk ahead, so that their
+  // latency hides behind the previous chunk's column phase.
+  constexpr int EB = (int)sizeof(XT);
+  uint32_t x_off[N1W];
+  sfor<0, N1W>([&](auto D) {
+    constexpr int d = D;
+    const int64_t col = rp_q1 + (N1W - 1 - d);
+    x_off[d] = col < sg.N1 ? (uint32_t)(((int64_t)rp_r * sg.N1 + col) * EB) : kOutOfRange;
+  });
+  constexpr int PASSES = C::CR / C::R;
+  XT xin[PASSES][N1W];
+  auto load_chunk = [&](int64_t rel_c) {
+    const int64_t rows = min((int64_t)C::CR, R - rel_c);
+    const auto rs = buf_rsrc(x + (rows > 0 ? rel_c : 0) * sg.N1,
+                             rows > 0 ? (uint32_t)(rows * sg.N1 * EB) : 0u);
+    sfor<0, PASSES>([&](auto PS) {
       constexpr int ps = PS;
-      const int64_t rel = rel0 + ps * C::R + rp_r;
-      const bool row_ok = rel < R;
-      float2 v[N1W];
       sfor<0, N1W>([&](auto D) {
         constexpr int d = D;
-        const int64_t col = rp_q1 + (N1W - 1 - d);
-        const bool ok = row_ok && col < sg.N1;
-        const int64_t idx = ok ? rel * sg.N1 + col : 0;
+        xin[ps][d] = load_buf<REAL>(rs, x_off[d] + (uint32_t)(ps * C::R * sg.N1 * EB));
+      });
+    });
+  };
+  // ---- row phase: CR rows x QW window columns of Z into LDS
+  auto row_phase = [&]() {
+    sfor<0, PASSES>([&](auto PS) {
+      constexpr int ps = PS;
+      float2 v[N1W];
+      sfor<0, N1W>([&](auto D) {
         if constexpr (REAL) {
-          const float t = x[idx];
-          v[d] = make_float2(ok ? t : 0.f, 0.f);
+          v[D] = make_float2(xin[ps][D], 0.f);
         } else {
-          const float2 t = x[idx];
-          v[d] = ok ? t : make_float2(0.f, 0.f);
+          v[D] = xin[ps][D];
         }
       });
       row_levels<N1W>(v, w1);
@@ -114,7 +130,15 @@ __global__ __launch_bounds__(64) void tree_stream_kernel(const void* __restrict_
       float2* zrow = zl + (ps * C::R + rp_r) * C::ZROW + rp_c * C::ZS;
       sfor<0, N1W>([&](auto K) { zrow[K] = v[K]; });
     });
-    __syncthreads();
+  };
+
+  load_chunk(0);
+  row_phase();
+  __syncthreads();
+  for (int c = 0; c < nchunks; ++c) {
+    const int64_t rel0 = (int64_t)c * C::CR;  // relative index of the chunk's first row
+    load_chunk(rel0 + C::CR);  // past the call's rows: zeros, no memory touched
+    __builtin_amdgcn_sched_barrier(0);
 
     // ---- column phase: the chunk's rows that this call carries
     sfor<0, C::CR>([&](auto STc) {
@@ -135,6 +159,10 @@ __global__ __launch_bounds__(64) void tree_stream_kernel(const void* __restrict_
       }
     });
     __syncthreads();
+    if (c + 1 < nchunks) {
+      row_phase();
+      __syncthreads();
+    }
   }
 
   // save the rings in absolute order (the same rotation as the load)
