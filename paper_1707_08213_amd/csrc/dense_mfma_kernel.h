@@ -95,11 +95,20 @@ __device__ __forceinline__ bf16x8 load_run(const __bf16* p) {
   return u4_to_bf(r);
 }
 
-__device__ __forceinline__ void store_nt(float2* p, float re, float im) {
+// One output value. Non-temporal where a store instruction covers whole
+// 128-byte lines (16 consecutive k1 per window, n1 >= 16); for n1 = 8 a line
+// is two k0 rows written by two instructions, and plain stores let L2 merge
+// them before the write-back.
+template <bool NT>
+__device__ __forceinline__ void store_out(float2* p, float re, float im) {
   f2v t;
   t.x = re;
   t.y = im;
-  __builtin_nontemporal_store(t, reinterpret_cast<f2v*>(p));
+  if constexpr (NT) {
+    __builtin_nontemporal_store(t, reinterpret_cast<f2v*>(p));
+  } else {
+    *reinterpret_cast<f2v*>(p) = t;
+  }
 }
 
 template <int N0W, int N1W, bool REAL>
@@ -291,8 +300,8 @@ __device__ __forceinline__ void dense_fwd_tile(const void* __restrict__ xv, floa
           // rows 16 MT + 4 lg + i = (k0, re/im) interleaved: two k0 per lane
           if (ok) {
             const int k0a = 8 * MT + 2 * lg;
-            store_nt(dst + k0a * N1W, acc[0], acc[1]);
-            store_nt(dst + (k0a + 1) * N1W, acc[2], acc[3]);
+            store_out<(N1W >= 16)>(dst + k0a * N1W, acc[0], acc[1]);
+            store_out<(N1W >= 16)>(dst + (k0a + 1) * N1W, acc[2], acc[3]);
           }
         });
       });
