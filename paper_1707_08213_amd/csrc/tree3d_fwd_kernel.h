@@ -39,7 +39,7 @@ using tree::column_levels;
 using tree::ColCfg;
 using tree::row_levels;
 using tree::sfor;
-using tree::store_buf_nt;
+using tree::store_buf;
 using tree::uniform_copy;
 using tree::uload;
 
@@ -47,6 +47,11 @@ template <int N0W, int N1W, int N2W, bool REAL>
 struct Tree3Cfg {
   static constexpr int NK = N1W * N2W;       // (k1, k2) pairs of a window
   static constexpr int QW = 64 / NK;         // windows per strip (along axis 2)
+  // non-temporal stores only where one store instruction writes whole
+  // 128-byte lines of a window (NK complex64 values per k0 row, NK >= 16);
+  // narrower rows take plain stores, which L2 merges (128^3 / 16x2x2:
+  // 817 us with non-temporal partial lines)
+  static constexpr bool NT_STORES = NK >= 16;
   static constexpr int RING = N0W > 1 ? N0W / 2 : 1;
   static constexpr int RA = N2W;             // plane rows per pass A (QW*N1W lanes per row)
   static constexpr int RB = N1W;             // plane rows per pass B (QW*N2W lanes per row)
@@ -193,7 +198,7 @@ __device__ __forceinline__ void tree3_fwd_tile(const void* __restrict__ xv, floa
       const auto out = buf_rsrc(ystrip + (row_store ? q0 : 0) * y_row_stride,
                                 row_store ? strip_bytes : 0u);
       column_levels<N0W, 1, st % C::RING>(z, ring, lanefac, lw, tw.w0, [&](auto J, float2 v) {
-        store_buf_nt(out, lane_off + J * C::NK * (int)sizeof(float2), v);
+        store_buf<C::NT_STORES>(out, lane_off + J * C::NK * (int)sizeof(float2), v);
       });
     });
     __syncthreads();

@@ -149,6 +149,10 @@ __global__ __launch_bounds__(64) void tree_stream_kernel(const void* __restrict_
         const bool row_store = q0 >= 0;
         const auto out = buf_rsrc(ystrip + (row_store ? q0 - q0_first : 0) * y_row_stride,
                                   row_store ? strip_bytes : 0u);
+        // Non-temporal stores for every n1. Plain stores for the narrow rows
+        // of n1 < 16, which help the long single-plan launches, measured
+        // slower for these short calls (1024-wide rows in 64-row pushes,
+        // 8 x 8: 295 -> 330 us per pass; 16 x 8: 469 -> 499 us).
         if constexpr (N0W == 1) {
           store_buf_nt(out, lane_off, z);
         } else {
