@@ -154,11 +154,10 @@ swdft::AdjGeom adj_geom(const swdft2d_plan_s* p) {
   g.nslabs = (int32_t)ceil_div(p->N0, g.S);
   g.batch = (int32_t)p->batch;
   g.scale = p->norm == SWDFT_NORM_ORTHO ? (float)(1.0 / std::sqrt((double)p->n0 * p->n1)) : 1.0f;
-  // Two resident waves per CU for n0 = 16: with more, the interleaved dy
-  // read streams of many tiles lower the HBM read rate by about 5% (measured
-  // on gfx950); with one, a wave cannot issue its loads and node operations
-  // fast enough.
-  g.wpc = env_int("SWDFT_ADJ_WPC", p->n0 == 16 ? 2 : 0);
+  // As many resident workgroups as fit. With four rows of dy in flight per
+  // wave (n0 <= 16) no cap was faster (16 x 256^2 / 16 x 16: 346 us uncapped,
+  // 367 us at two per CU); SWDFT_ADJ_WPC sets a cap.
+  g.wpc = env_int("SWDFT_ADJ_WPC", 0);
   g.lds_cu = lds_per_cu();
   if (g.lds_cu <= 0 || g.wpc < 0) g.wpc = 0;
   return g;

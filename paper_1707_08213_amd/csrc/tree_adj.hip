@@ -5,9 +5,14 @@ namespace swdft {
 
 int tree_adj_rows_per_chunk(int n0, int n1) {
   const int ring = n0 > 1 ? n0 / 2 : 1;
+  const int pf = tree::adj_prefetch_rows(n0);
   int cr = n1 > ring ? n1 : ring;
-  return cr > 2 ? cr : 2;
+  return cr > pf ? cr : pf;
 }
+
+static_assert(tree::AdjCfg<16, 16>::CR == 16 && tree::AdjCfg<2, 1>::CR == 4 &&
+                  tree::AdjCfg<32, 8>::CR == 16 && tree::AdjCfg<4, 2>::CR == 4,
+              "host and kernel rows per chunk agree");
 
 int tree_adj_columns_per_wave(int n0, int n1) {
   (void)n0;

@@ -22,8 +22,8 @@
 //
 // Mapping: like the forward kernel, one wave owns QW = 64/n1 window columns
 // and a slab of output rows of dx. Lane (c, k1) reads dy[q0][q1][k0][k1] for
-// all k0 (each load instruction covers whole 128-byte lines), two steps ahead
-// of use (register prefetch) so a wave keeps two rows of loads in flight.
+// all k0 (each load instruction covers whole 128-byte lines), PF steps ahead
+// of use (register prefetch) so a wave keeps PF rows of loads in flight.
 // The slab is primed by the n0-1 window rows below it. A strip's row adjoint
 // covers x columns [q1_0, q1_0 + QW + n1 - 1); columns near strip edges get
 // parts from neighbouring strips, so each wave writes its partial sums for
@@ -114,13 +114,17 @@ __device__ __forceinline__ float2 load_buf_nt(__amdgpu_buffer_rsrc_t r, uint32_t
   return make_float2(__uint_as_float(t.x), __uint_as_float(t.y));
 }
 
+// Rows of dy a wave keeps in flight: four up to n0 = 16, two for n0 = 32,
+// whose register rings leave no room for more.
+constexpr int adj_prefetch_rows(int n0) { return n0 <= 16 ? 4 : 2; }
+
 template <int N0W, int N1W>
 struct AdjCfg {
   static constexpr int M0 = ilog2(N0W);
   static constexpr int QW = 64 / N1W;
   static constexpr int R = N1W;
   static constexpr int RING = N0W > 1 ? N0W / 2 : 1;
-  static constexpr int PF = 2;                              // prefetch depth (rows)
+  static constexpr int PF = adj_prefetch_rows(N0W);         // prefetch depth (rows)
   static constexpr int CR0 = R > RING ? R : RING;
   static constexpr int CR = CR0 > PF ? CR0 : PF;           // rows per chunk
   static constexpr int ZS = N1W + 1;
