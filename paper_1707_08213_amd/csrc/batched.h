@@ -45,7 +45,9 @@ struct BatchArgs {
 
 // Persistent class kernels exist for n0, n1 in {8, 16, 32}.
 bool batched_shape_supported(int n0, int n1);
-// lanes per column stream of the tree path the batched kernels compile
+// Lanes per column stream of the tree path the batched kernels compile (fixed
+// at compile time, independent of the single-plan default).
+constexpr int batched_kg(int n0, int n1) { return (n0 == 32 || n0 == 8 || n1 == 8) ? 2 : 1; }
 int batched_tree_kg(int n0, int n1);
 // kernel symbol of a class (nullptr if none)
 const void* batched_tree_symbol(int n0, int n1, bool real_input);

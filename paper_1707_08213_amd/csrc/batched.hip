@@ -24,7 +24,7 @@ bool batched_shape_supported(int n0, int n1) {
 
 // Lanes per column stream of the class kernels: the single-plan default, so
 // that a batched image and a single plan of it give identical bits.
-int batched_tree_kg(int n0, int n1) { return tree_fwd_default_kg(n0, n1); }
+int batched_tree_kg(int n0, int n1) { return batched_kg(n0, n1); }
 
 const void* batched_tree_symbol(int n0, int n1, bool real_input) {
   return real_input ? batched_tree_symbol_r(n0, n1) : batched_tree_symbol_c(n0, n1);

@@ -17,7 +17,7 @@ __device__ __forceinline__ int next_item(unsigned* counter) {
 
 template <int N0W, int N1W, bool REAL>
 __global__ __launch_bounds__(64) void tree_class_kernel(BatchArgs a) {
-  constexpr int KG = (N0W == 32 || N0W == 8 || N1W == 8) ? 2 : 1;  // as batched_tree_kg
+  constexpr int KG = batched_kg(N0W, N1W);
   using C = tree::TreeCfg<N0W, N1W, REAL, KG>;
   __shared__ float2 zl[C::LDS_FLOAT2];
   for (int it = next_item(a.counter); it < a.count; it = next_item(a.counter)) {

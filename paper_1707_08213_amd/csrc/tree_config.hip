@@ -73,14 +73,20 @@ struct TreeCap {
 };
 
 // Shapes whose default is one workgroup per CU (measured on gfx950): unsplit
-// n0 = 16 streams with one wave per strip (n1 >= 16), and split streams of
-// n1 = 8 windows (n0 >= 16) with two waves per strip. Other combinations
-// were not faster than the uncapped launch.
+// n0 = 16 and n0 = 32 streams (n1 >= 16), split streams of n1 = 8 windows
+// (n0 >= 16) with two waves per strip, and n0 = 64 with n1 <= 8. The other
+// radix-2 shapes default to two per CU.
 bool capped_by_default(int n0, int n1, int kg) {
-  return (n0 == 16 && kg == 1) || (n0 >= 16 && n1 == 8 && kg == 2);
+  return (n0 == 16 && kg == 1) || (n0 >= 16 && n1 == 8 && kg == 2) || (n0 == 32 && kg == 1) ||
+         (n0 == 64 && n1 <= 8);
 }
 
-bool two_waves_by_default(int n0, int n1, int kg) { return n0 >= 16 && n1 == 8 && kg == 2; }
+// Two waves per strip: capped n1 = 8 split streams, 32 x 32 unsplit (1024^2:
+// 1550 -> 1475 us) and n0 = 64 with n1 <= 8 (64 x 8: 774 -> 681 us).
+bool two_waves_by_default(int n0, int n1, int kg) {
+  return (n0 >= 16 && n1 == 8 && kg == 2) || (n0 == 32 && n1 == 32 && kg == 1) ||
+         (n0 == 64 && n1 <= 8);
+}
 
 TreeCap tree_cap(const swdft2d_plan_s* p, int kg) {
   const int64_t columns =
@@ -90,10 +96,17 @@ TreeCap tree_cap(const swdft2d_plan_s* p, int kg) {
   c.wpc = p->tree_wpc >= 0 ? p->tree_wpc : env_int("SWDFT_TREE_WPC", -1);
   if (c.wpc < 0) {
     c.wpc = 0;
-    if (mixed_window(p) ? p->n0 * p->n1 >= 144 : capped_by_default(p->n0, p->n1, kg)) {
-      // mixed-radix windows of 12 x 12 and up: two resident workgroups per CU
-      // (1024 x 1024: 12 x 12 259 -> 246 us, 24 x 24 1026 -> 914 us)
-      const int wpc = mixed_window(p) ? 2 : 1;
+    // one resident workgroup per CU for the shapes above; two for the others
+    // (1024 x 1024: 8 x 8 105 -> 87 us, 4 x 16 107 -> 88 us), and for
+    // mixed-radix windows of 12 x 12 and up (12 x 12 259 -> 246 us, 24 x 24
+    // 1026 -> 914 us); none where the rounds would not fill
+    int wpc = 0;
+    if (mixed_window(p)) {
+      wpc = p->n0 * p->n1 >= 144 ? 2 : 0;
+    } else {
+      wpc = capped_by_default(p->n0, p->n1, kg) ? 1 : 2;
+    }
+    if (wpc > 0) {
       const int64_t s = filling_slabs(columns, ncu * wpc);
       if (s > 0) c = TreeCap{wpc, s};
     }
@@ -104,10 +117,11 @@ TreeCap tree_cap(const swdft2d_plan_s* p, int kg) {
   return c;
 }
 
-// Waves per workgroup sharing a strip: two for capped n1 = 8 split streams
-// (one wave's issue rate would bound the tile: 1024x1024 / 16x8 went from 5.5
-// to 6.7-6.9 TB/s, 2048x512 / 32x8 from 5.4 to 5.55); one otherwise (for
-// unsplit n0 = 16 streams a second wave lowered the write rate by 11%).
+// Waves per workgroup sharing a strip: two for the capped shapes of
+// two_waves_by_default (one wave's issue rate would bound the tile:
+// 1024x1024 / 16x8 went from 5.5 to 6.7-6.9 TB/s, 2048x512 / 32x8 from 5.4 to
+// 5.55); one otherwise (for unsplit n0 = 16 streams a second wave lowered the
+// write rate by 11%).
 int32_t tree_wv(const swdft2d_plan_s* p, int kg, int wpc) {
   if (mixed_window(p)) return 1;
   int wv = p->tree_wv > 0 ? p->tree_wv : env_int("SWDFT_TREE_WV", 0);

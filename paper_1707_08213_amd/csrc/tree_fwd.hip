@@ -14,15 +14,17 @@ int tree_fwd_rows_per_chunk(int n0, int n1, int kg, int wv) {
   return rows_per_pass > ring ? rows_per_pass : ring;
 }
 
-// A stream is split over two lanes when its register rings would otherwise
-// limit the kernel to one wave per SIMD (n0 = 32); for n0 = 8, whose short
-// output rows per wave need more waves in flight; and for n1 = 8, where the
-// two lanes of a stream write adjacent 64-byte k0 rows, so each store
-// instruction covers whole 128-byte lines.
-// n0 = 64 is built with one split per n1 (tree::tree_kg64).
+// A stream is split over two lanes for n0 = 8, whose short output rows per
+// wave need more waves in flight; for n1 = 8, where the two lanes of a stream
+// write adjacent 64-byte k0 rows, so each store instruction covers whole
+// 128-byte lines; for n0 = 32 with n1 <= 8; and for 16 x 4 (1024^2: 127 ->
+// 104 us). n0 = 32 with n1 >= 16 keeps whole streams on whole columns (32 x 16:
+// 783 -> 637 us). n0 = 64 is built with one split per n1 (tree::tree_kg64).
 int tree_fwd_default_kg(int n0, int n1) {
   if (n0 == 64) return tree::tree_kg64(n1);
-  return (n0 >= 8 && n1 <= 32 && (n0 == 32 || n0 == 8 || n1 == 8)) ? 2 : 1;
+  if (n0 == 32) return n1 <= 8 ? 2 : 1;
+  if (n0 == 16 && n1 == 4) return 2;
+  return (n0 == 8 && n1 <= 32) || (n0 >= 8 && n1 == 8) ? 2 : 1;
 }
 
 int tree_fwd_resident_waves(int wpc, int ncu) { return wpc > 0 && ncu > 0 ? wpc * ncu : 0; }

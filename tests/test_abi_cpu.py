@@ -315,11 +315,11 @@ def test_stream_validation():
 
 
 @pytest.mark.parametrize("n0,n1,kg,cols,wv", [
-    (64, 64, 1, 1, 2), (64, 32, 2, 1, 1), (64, 16, 4, 1, 1), (64, 8, 8, 1, 1), (64, 4, 8, 2, 1),
+    (64, 64, 1, 1, 2), (64, 32, 2, 1, 1), (64, 16, 4, 1, 1), (64, 8, 8, 1, 2), (64, 4, 8, 2, 2),
     (64, 1, 8, 8, 1), (32, 64, 1, 1, 1), (4, 64, 1, 1, 1)])
 def test_window64_tree_shapes(n0, n1, kg, cols, wv):
     """n0 = 64 splits each stream over KG = min(8, 64/n1) lanes; 64 x 64, whose
-    stream stays whole, runs two waves per strip."""
+    stream stays whole, and the capped n1 <= 8 shapes run two waves per strip."""
     st, h = make_plan(200, 300, n0, n1)
     assert st == 0
     buf = ctypes.create_string_buffer(512)
