@@ -297,3 +297,23 @@ def test_write_probe_fills_exactly(swd, offset, count):
     inside = v[offset:offset + count]
     assert np.all(inside[:, 0] == 1.0) and np.all(inside[:, 1] == -1.0)
     assert np.all(v[:offset] == 0) and np.all(v[offset + count:] == 0)
+
+
+@pytest.mark.parametrize("n0,n1", [(8, 8), (8, 16), (32, 16), (32, 32), (4, 16), (16, 4), (64, 8),
+                                   (8, 64), (16, 8), (4, 4)], ids=lambda v: str(v))
+def test_default_launch_1024_sampled(swd, orc, n0, n1):
+    """The default launch at 1024 x 1024 (caps of one or two workgroups per CU,
+    whole streams or split, one or two waves per strip, as the plan picks):
+    256 sampled windows, corners and edges included, against the oracle."""
+    x = workloads.normal_real((1024, 1024), seed=1600 + n0 + n1)
+    xt = torch.from_numpy(x).cuda()
+    p = swd.Plan(1024, 1024, n0, n1)
+    print(f"[case] {p.describe()}", flush=True)
+    y = p.forward(xt.unsqueeze(0))[0]
+    P0, P1 = 1024 - n0 + 1, 1024 - n1 + 1
+    q0, q1 = workloads.window_sample(P0, P1, 256, 1601)
+    got = y[torch.from_numpy(q0).cuda(), torch.from_numpy(q1).cuda()].cpu().numpy()
+    del y
+    torch.cuda.empty_cache()
+    ref = orc.swdft2d(x.astype(np.float64), n0, n1, windows=(q0, q1))
+    assert rel_err(got, ref) <= TOL_F32
