@@ -34,7 +34,9 @@ __host__ __device__ constexpr int direct_tile_elems(int n0, int n1, int wb) {
   return n0 * (wb + n1 - 1);
 }
 
-template <bool REAL>
+// POW2: both sides are powers of two and (j k) mod n is a mask; otherwise it
+// is stepped (e += k, minus n on overflow) for any n.
+template <bool REAL, bool POW2>
 __global__ __launch_bounds__(kDirectThreads) void direct_f64_kernel(const void* __restrict__ xv,
                                                                     double2* __restrict__ y,
                                                                     DirectGeom g, TwiddlesF64 tw,
@@ -75,15 +77,20 @@ __global__ __launch_bounds__(kDirectThreads) void direct_f64_kernel(const void* 
     const int k0 = (t / n1) % n0;
     const int k1 = t % n1;
     double ar = 0.0, ai = 0.0;
-    int e0 = 0;  // (j0 k0) mod n0, stepped (any n, not only powers of two)
+    int e0 = 0;  // (j0 k0) mod n0
     for (int j0 = 0; j0 < n0; ++j0) {
       const double2* xrow = xs + j0 * cols + w;
       double sr = 0.0, si = 0.0;
       int e1 = 0;  // (j1 k1) mod n1
       for (int j1 = 0; j1 < n1; ++j1) {
-        const double2 tw1 = w1s[e1];
-        e1 += k1;
-        if (e1 >= n1) e1 -= n1;
+        double2 tw1;
+        if constexpr (POW2) {
+          tw1 = w1s[(j1 * k1) & (n1 - 1)];
+        } else {
+          tw1 = w1s[e1];
+          e1 += k1;
+          if (e1 >= n1) e1 -= n1;
+        }
         const double2 v = xrow[j1];
         if constexpr (REAL) {
           sr += v.x * tw1.x;
@@ -93,9 +100,14 @@ __global__ __launch_bounds__(kDirectThreads) void direct_f64_kernel(const void* 
           si += v.x * tw1.y + v.y * tw1.x;
         }
       }
-      const double2 tw0 = w0s[e0];
-      e0 += k0;
-      if (e0 >= n0) e0 -= n0;
+      double2 tw0;
+      if constexpr (POW2) {
+        tw0 = w0s[(j0 * k0) & (n0 - 1)];
+      } else {
+        tw0 = w0s[e0];
+        e0 += k0;
+        if (e0 >= n0) e0 -= n0;
+      }
       ar += tw0.x * sr - tw0.y * si;
       ai += tw0.x * si + tw0.y * sr;
     }
@@ -113,12 +125,21 @@ hipError_t launch_direct_f64(int n0, int n1, bool real_input, const void* x, dou
   const int64_t nb = (int64_t)g.batch * g.P0 * g.ntiles1;
   if (nb > 0x7fffffff) return hipErrorInvalidConfiguration;
   const size_t lds = (size_t)(direct_tile_elems(n0, n1, wb) + n0 + n1) * sizeof(double2);
+  const bool pow2 = (n0 & (n0 - 1)) == 0 && (n1 & (n1 - 1)) == 0;
+  const dim3 grid((unsigned)nb), block(kDirectThreads);
   if (real_input) {
-    hipLaunchKernelGGL(direct_f64_kernel<true>, dim3((unsigned)nb), dim3(kDirectThreads), lds,
-                       stream, x, y, g, tw, wb);
+    if (pow2) {
+      hipLaunchKernelGGL((direct_f64_kernel<true, true>), grid, block, lds, stream, x, y, g, tw, wb);
+    } else {
+      hipLaunchKernelGGL((direct_f64_kernel<true, false>), grid, block, lds, stream, x, y, g, tw, wb);
+    }
   } else {
-    hipLaunchKernelGGL(direct_f64_kernel<false>, dim3((unsigned)nb), dim3(kDirectThreads), lds,
-                       stream, x, y, g, tw, wb);
+    if (pow2) {
+      hipLaunchKernelGGL((direct_f64_kernel<false, true>), grid, block, lds, stream, x, y, g, tw, wb);
+    } else {
+      hipLaunchKernelGGL((direct_f64_kernel<false, false>), grid, block, lds, stream, x, y, g, tw,
+                         wb);
+    }
   }
   return hipGetLastError();
 }
