@@ -39,7 +39,8 @@ bool is_live_stream(swdft2d_stream_t s) {
 }
 
 int64_t stream_nstrips(const swdft2d_stream_s* s) {
-  return ceil_div(s->P1, swdft::tree_fwd_columns_per_wave(s->n0, s->n1, 1));
+  return ceil_div(s->P1, swdft::tree_fwd_columns_per_wave(s->n0, s->n1,
+                                                         swdft::tree_stream_kg(s->n0)));
 }
 
 // Window rows that complete when `rows` rows follow `before` rows: every window

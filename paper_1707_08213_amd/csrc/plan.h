@@ -90,6 +90,9 @@ hipError_t launch_tree_mixed_r(int n0, int n1, const void* x, float2* y, const T
 hipError_t launch_tree_mixed_c(int n0, int n1, const void* x, float2* y, const TreeGeom& g,
                                const TwiddlesF32& tw, hipStream_t s);
 
+// Lanes per column stream of the streaming kernel for windows of height n0.
+int tree_stream_kg(int n0);
+
 namespace host {
 
 // The plan's window has a side that is not a power of two (mixed-radix tree).

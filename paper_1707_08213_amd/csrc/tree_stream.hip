@@ -1,17 +1,22 @@
 // Dispatch of the streaming 2D tree kernel by window shape, and the fill
 // kernel that clears a stream's resident state.
+#include "plan.h"
 #include "tree_stream_kernel.h"
 
 namespace swdft {
 
+int tree_stream_kg(int n0) { return tree::stream_kg(n0); }
+
+// Ring values per lane of the resident state (a split stream keeps its
+// residue's share).
 int tree_stream_state_slots(int n0) {
   switch (n0) {
-    case 1: return tree::ColCfg<1, 1>::RING_TOTAL;
-    case 2: return tree::ColCfg<2, 1>::RING_TOTAL;
-    case 4: return tree::ColCfg<4, 1>::RING_TOTAL;
-    case 8: return tree::ColCfg<8, 1>::RING_TOTAL;
-    case 16: return tree::ColCfg<16, 1>::RING_TOTAL;
-    case 32: return tree::ColCfg<32, 1>::RING_TOTAL;
+    case 1: return tree::ColCfg<1, tree::stream_kg(1)>::RING_TOTAL;
+    case 2: return tree::ColCfg<2, tree::stream_kg(2)>::RING_TOTAL;
+    case 4: return tree::ColCfg<4, tree::stream_kg(4)>::RING_TOTAL;
+    case 8: return tree::ColCfg<8, tree::stream_kg(8)>::RING_TOTAL;
+    case 16: return tree::ColCfg<16, tree::stream_kg(16)>::RING_TOTAL;
+    case 32: return tree::ColCfg<32, tree::stream_kg(32)>::RING_TOTAL;
     default: return 0;
   }
 }

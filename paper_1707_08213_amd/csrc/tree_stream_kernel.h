@@ -7,8 +7,9 @@
 // costs the 2(n0-1) node operations per stream of Eq. (8) and completes one
 // row of P1 windows as soon as it arrives.
 //
-// One wave owns QW = 64/n1 window columns (unsplit streams, KG = 1) and
-// processes the R rows of one call: the row levels (Eq. (5)) per position into
+// One wave owns QW = 64/(n1 KG) window columns (streams split over KG = 2
+// lanes from n0 = 8 on, as in the single-image kernel) and processes the R
+// rows of one call: the row levels (Eq. (5)) per position into
 // LDS (inputs loaded a chunk ahead), then the column levels with the rings
 // loaded from, and at the end saved to, the resident state. The state is kept in absolute row order: the nodes
 // of tree p at level u-1 sit in tree slot (p mod s_u). The unrolled column phase
@@ -23,13 +24,20 @@
 namespace swdft {
 namespace tree {
 
+// Lanes per column stream: two from n0 = 8 on (as the single-image kernel's
+// split streams), which doubles the strips of a call and halves each lane's
+// column work per row; calls are short, so their time is set by how long one
+// wave takes for its rows.
+constexpr int stream_kg(int n0) { return n0 >= 8 ? 2 : 1; }
+
 template <int N0W, int N1W, bool REAL>
 __global__ __launch_bounds__(64) void tree_stream_kernel(const void* __restrict__ xv,
                                                          float2* __restrict__ y,
                                                          float2* __restrict__ state, StreamGeom g,
                                                          TwiddlesF32 tw) {
-  using C = TreeCfg<N0W, N1W, REAL, 1>;
-  using CC = ColCfg<N0W, 1>;
+  constexpr int KG = stream_kg(N0W);
+  using C = TreeCfg<N0W, N1W, REAL, KG>;
+  using CC = ColCfg<N0W, KG>;
   __shared__ float2 zl[C::LDS_FLOAT2];
   const int lane = threadIdx.x;
   const int strip = blockIdx.x;
@@ -51,22 +59,40 @@ __global__ __launch_bounds__(64) void tree_stream_kernel(const void* __restrict_
   const int rp_r = lane / C::QW;
   const int rp_c = lane % C::QW;
   const int64_t rp_q1 = q1_0 + rp_c;
-  // column-phase roles: lane (c, k1)
-  const int cp_c = lane / N1W;
+  // column-phase roles: lane (c, residue, k1)
+  const int cp_c = lane / (N1W * KG);
+  const int cp_res = (lane / N1W) % KG;
   const int cp_k1 = lane % N1W;
   float2* ystrip = y + q1_0 * (N0W * N1W);
   const int64_t y_row_stride = sg.P1 * (N0W * N1W);
   const uint32_t strip_bytes =
       (uint32_t)(min((int64_t)C::QW, sg.P1 - q1_0) * (N0W * N1W * (int)sizeof(float2)));
-  const uint32_t lane_off = (uint32_t)((cp_c * (N0W * N1W) + cp_k1) * (int)sizeof(float2));
+  const uint32_t lane_off =
+      (uint32_t)((cp_c * (N0W * N1W) + cp_res * N1W + cp_k1) * (int)sizeof(float2));
 
   // resident state: slot k of this lane at state[k * state_stride + strip * 64 + lane]
   float2* st_lane = state + (int64_t)strip * 64 + lane;
   const int64_t state_stride = (int64_t)sg.nstrips * 64;
 
+  // per-lane twiddle factors of a split stream (as in the single-image kernel)
   float2 lanefac[CC::M0 + 1];
   float2 lw[CC::M0 + 1][CC::LW];
-  sfor<0, CC::M0 + 1>([&](auto U) { lanefac[U] = make_float2(1.f, 0.f); });
+  lanefac[0] = make_float2(1.f, 0.f);
+  sfor<1, CC::M0 + 1>([&](auto U) {
+    constexpr int u = U;
+    if constexpr (KG > 1) {
+      lanefac[u] = w0[(cp_res & ((1 << u) - 1)) * (N0W >> u)];
+    } else {
+      lanefac[u] = make_float2(1.f, 0.f);
+    }
+  });
+  sfor<1, CC::M0 + 1>([&](auto U) {
+    constexpr int u = U;
+    sfor<0, CC::LW>([&](auto J) {
+      constexpr int j = J;
+      if constexpr (CC::folded(u, j)) lw[u][j] = cmul(lanefac[u], uload(w0 + CC::tw_index(u, j)));
+    });
+  });
 
   // ring of level u-1: s_u tree slots of held(u-1) nodes each; static tree
   // slot t holds the tree whose absolute row index is congruent to
@@ -156,8 +182,8 @@ __global__ __launch_bounds__(64) void tree_stream_kernel(const void* __restrict_
         if constexpr (N0W == 1) {
           store_buf_nt(out, lane_off, z);
         } else {
-          column_levels<N0W, 1, st % C::RING>(z, ring, lanefac, lw, w0, [&](auto J, float2 v) {
-            store_buf_nt(out, lane_off + J * N1W * (int)sizeof(float2), v);
+          column_levels<N0W, KG, st % C::RING>(z, ring, lanefac, lw, w0, [&](auto J, float2 v) {
+            store_buf_nt(out, lane_off + (KG * J) * N1W * (int)sizeof(float2), v);
           });
         }
       }
@@ -185,6 +211,7 @@ __global__ __launch_bounds__(64) void tree_stream_kernel(const void* __restrict_
 template <int N0W, int N1W, bool REAL>
 hipError_t launch_stream_one(const void* x, float2* y, float2* state, const StreamGeom& g,
                              const TwiddlesF32& tw, hipStream_t stream) {
+  static_assert(64 % (N1W * stream_kg(N0W)) == 0, "a wave holds whole split streams");
   hipLaunchKernelGGL((tree_stream_kernel<N0W, N1W, REAL>), dim3((unsigned)g.nstrips), dim3(64), 0,
                      stream, x, y, state, g, tw);
   return hipGetLastError();
