@@ -350,7 +350,7 @@ def test_window64_limits_of_other_paths():
 
 @pytest.mark.parametrize("N,n,slab,slabs", [
     (100, 16, 16, 6),     # 22 strips: one-chunk slabs rather than 44 long ones
-    (100, 32, 64, 2),     # split streams: 64-row chunks
+    (100, 32, 128, 1),    # split streams on two waves: 128-row chunks
     (1024, 16, 1024, 1),  # one workgroup per CU walking whole columns
 ])
 def test_tree_slab_rule(N, n, slab, slabs):
@@ -396,3 +396,18 @@ def test_mixed_radix_plan_rules():
     s = ctypes.c_void_p()
     assert lib.swdft2d_stream_create(ctypes.byref(s), 100, 12, 8, _lib.SWDFT_R32) == \
         S["SWDFT_E_NOT_POW2"]
+
+
+@pytest.mark.parametrize("N,n,kg,wv", [(100, 32, 2, 2), (100, 8, 1, 1), (100, 16, 1, 1),
+                                       (1024, 32, 1, 2), (1024, 8, 2, 1)])
+def test_tree_small_image_split(N, n, kg, wv):
+    """Small images (fewer tiles than compute units) split 32 x 32 streams over
+    two lanes and two waves and keep 8 x 8 streams whole; large images keep
+    the large-image defaults."""
+    st, h = make_plan(N, N, n, n)
+    assert st == 0
+    buf = ctypes.create_string_buffer(512)
+    assert lib.swdft2d_describe(h, buf, 512) == 0
+    d = buf.value.decode()
+    assert f" kg={kg} " in d and f" waves_per_strip={wv} " in d, d
+    lib.swdft2d_destroy(h)
