@@ -9,14 +9,14 @@
 //
 // One wave owns QW = 64/(n1 KG) window columns (streams split over KG = 2
 // lanes from n0 = 8 on, as in the single-image kernel) and processes the R
-// rows of one call: the row levels (Eq. (5)) per position into
-// LDS (inputs loaded a chunk ahead), then the column levels with the rings
-// loaded from, and at the end saved to, the resident state. The state is kept in absolute row order: the nodes
-// of tree p at level u-1 sit in tree slot (p mod s_u). The unrolled column phase
-// uses static ring slots (relative step mod s_u), so the load and the save
-// rotate by (first row mod s_u) through computed memory addresses. Steps past
-// the call's last row are skipped (a wave-uniform branch), so calls may
-// carry any number of rows.
+// rows of one call: the row levels (Eq. (5)) per position into LDS (inputs
+// loaded a chunk ahead), then the column levels with the rings loaded from,
+// and at the end saved to, the resident state. The state is kept in absolute
+// row order: the nodes of tree p at level u-1 sit in tree slot (p mod s_u).
+// The unrolled column phase uses static ring slots (relative step mod s_u),
+// so the load and the save rotate by (first row mod s_u) through computed
+// memory addresses. Steps past the call's last row are skipped (a
+// wave-uniform branch), so calls may carry any number of rows.
 #pragma once
 
 #include "tree_fwd_kernel.h"
