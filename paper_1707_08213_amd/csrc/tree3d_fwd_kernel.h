@@ -20,9 +20,10 @@
 //    down the slab through the m0 levels of axis 0 (Eq. (6) with the node
 //    index ranging over (k1, k2) pairs), storing the last level at once.
 //  * Output y[b][q0][q1][q2][k0][k1][k2]: for each k0 the 64 lanes store QW
-//    runs of n1*n2 complex values (whole 128-byte lines when n1*n2 >= 16)
-//    through a buffer resource per output row (empty for priming rows, and
-//    ending at the last window of the strip).
+//    runs of n1*n2 complex values through a buffer resource per output row
+//    (empty for priming rows, and ending at the last window of the strip);
+//    non-temporal stores when a run is whole 128-byte lines (n1*n2 >= 16),
+//    plain stores below that.
 //  * Inputs of the next chunk are loaded before the column phase of the
 //    current one (the loop is rotated as in the 2D kernel), from clamped
 //    in-range addresses, with zeros selected past the volume's edges.

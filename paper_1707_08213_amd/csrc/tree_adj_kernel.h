@@ -204,16 +204,23 @@ __global__ __launch_bounds__(64) void tree_adj_kernel(const float2* __restrict__
     sfor<0, C::CR>([&](auto STc) {
       constexpr int st = STc;
       constexpr int slot = st % C::PF;
-      float2 gcur[N0W];
-      sfor<0, N0W>([&](auto K) { gcur[K] = pf[slot][K]; });
-      load_step(cbase + st + C::PF, pf[slot]);
+      // p mod (n0/2): p_top + 1 is a multiple of CR, hence of n0/2
+      constexpr int pm = (C::RING - 1 - (st % C::RING));
       float2 dz;
-      if constexpr (N0W == 1) {
-        dz = gcur[0];
+      if constexpr (N0W >= 32) {
+        // the rings fill the registers: use the prefetched row in place and
+        // refill its slot afterwards (no second copy of 32 values)
+        dz = column_levels_adj<N0W, pm>(pf[slot], ring, tw.w0);
+        load_step(cbase + st + C::PF, pf[slot]);
       } else {
-        // p mod (n0/2): p_top + 1 is a multiple of CR, hence of n0/2
-        constexpr int pm = (C::RING - 1 - (st % C::RING));
-        dz = column_levels_adj<N0W, pm>(gcur, ring, tw.w0);
+        float2 gcur[N0W];
+        sfor<0, N0W>([&](auto K) { gcur[K] = pf[slot][K]; });
+        load_step(cbase + st + C::PF, pf[slot]);
+        if constexpr (N0W == 1) {
+          dz = gcur[0];
+        } else {
+          dz = column_levels_adj<N0W, pm>(gcur, ring, tw.w0);
+        }
       }
       zl[st * C::ZROW + cp_c * C::ZS + cp_k1] = dz;
     });
