@@ -123,6 +123,10 @@ TreeCap tree_cap(const swdft2d_plan_s* p, int kg) {
     int wpc = 0;
     if (mixed_window(p)) {
       wpc = p->n0 * p->n1 >= 144 ? 2 : 0;
+      // about one tile per CU when the strips, in one or two slabs, fill one
+      // round of CUs (1024 x 1024: 12 x 16 319 -> 278 us, 24 x 8 322 -> 274 us)
+      for (int64_t s = 1; wpc == 2 && s <= 2; ++s)
+        if (columns * s <= ncu && columns * s * 10 >= ncu * 9) return TreeCap{2, s};
     } else {
       wpc = capped_by_default(p->n0, p->n1, kg) ? 1 : 2;
     }
