@@ -117,7 +117,7 @@ TreeCap tree_cap(const swdft2d_plan_s* p, int kg) {
   if (c.wpc < 0) {
     c.wpc = 0;
     // one resident workgroup per CU for the shapes above; two for the others
-    // (1024 x 1024: 8 x 8 105 -> 88 us, 8 x 16 201 -> 183 us), and for
+    // (1024 x 1024, alternating A/B: 8 x 8 102 -> 85-92 us, 8 x 16 198 -> 193 us), and for
     // mixed-radix windows of 12 x 12 and up (12 x 12 259 -> 246 us, 24 x 24
     // 1026 -> 914 us); none where the rounds would not fill
     int wpc = 0;
