@@ -170,7 +170,10 @@ int32_t tree_slab(const swdft2d_plan_s* p, int kg, int wv, const TreeCap& cap) {
     if (cap.wpc > 0 && cap.slabs > 0) {
       S = ceil_div(p->P0, cap.slabs);
     } else {
-      S = ceil_div(p->P0 * nstrips * p->batch, 4096);
+      // about 4096 tiles; about 1024 for the uncapped mixed-radix windows
+      // (1024 x 1024 / 9 x 9, alternating A/B: 159-165 -> 138-142 us)
+      const int64_t tiles = mixed_window(p) ? 1024 : 4096;
+      S = ceil_div(p->P0 * nstrips * p->batch, tiles);
       S = std::max<int64_t>(S, 4 * (int64_t)(p->n0 - 1));
       // Small images: rather one chunk per slab (priming rows and all) than
       // fewer tiles than CUs, whose sequential walks down the slab then set
