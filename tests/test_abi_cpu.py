@@ -411,3 +411,21 @@ def test_tree_small_image_split(N, n, kg, wv):
     d = buf.value.decode()
     assert f" kg={kg} " in d and f" waves_per_strip={wv} " in d, d
     lib.swdft2d_destroy(h)
+
+
+@pytest.mark.parametrize("n0,n1,slabs,waves", [
+    (12, 16, 1, 253),    # strips fill one round of CUs: whole columns
+    (24, 8, 2, 256),     # two slabs fill one round
+    (12, 12, 5, 1015),   # capped at two per CU, slabs fill its rounds
+    (9, 9, 7, 1022),     # uncapped, about 1024 tiles
+])
+def test_mixed_radix_launch_rules(n0, n1, slabs, waves):
+    """Launch shapes of the mixed-radix tree at 1024 x 1024 (256 compute units
+    assumed without a device; the resident cap itself needs a device)."""
+    st, h = make_plan(1024, 1024, n0, n1)
+    assert st == 0
+    buf = ctypes.create_string_buffer(512)
+    assert lib.swdft2d_describe(h, buf, 512) == 0
+    d = buf.value.decode()
+    assert f" slabs={slabs} " in d and f" waves={waves} " in d, d
+    lib.swdft2d_destroy(h)
