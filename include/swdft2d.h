@@ -234,8 +234,8 @@ typedef struct swdft2d_stream_s* swdft2d_stream_t;
  * C32 (E_DTYPE); n0, n1 powers of two (E_NOT_POW2); n1 <= N1 and
  * n_i <= SWDFT_MAX_WINDOW_ADJ (E_WINDOW); N1 <= SWDFT_MAX_ROW (E_OVERFLOW).
  * Touches no GPU. The device state, 8 * max(m0 n0 / 2, 1) * 64 bytes per strip
- * of 64/n1 window columns for n0 < 8 (about 4 m0 n0 n1 (N1 - n1 + 1) bytes;
- * from n0 = 8 on each stream is split over two lanes, which keep 1.2 to 1.33
+ * of 64/n1 window columns for n0 < 4 (about 4 m0 n0 n1 (N1 - n1 + 1) bytes;
+ * from n0 = 4 on each stream is split over two lanes, which keep 1.2 to 1.5
  * times that in all), is allocated with hipMalloc at the first push, on the
  * current device, and cleared there with a kernel. */
 swdft_status_t swdft2d_stream_create(swdft2d_stream_t* out, int64_t N1, int32_t n0, int32_t n1,

@@ -8,7 +8,7 @@
 // row of P1 windows as soon as it arrives.
 //
 // One wave owns QW = 64/(n1 KG) window columns (streams split over KG = 2
-// lanes from n0 = 8 on, as in the single-image kernel) and processes the R
+// lanes from n0 = 4 on) and processes the R
 // rows of one call: the row levels (Eq. (5)) per position into LDS (inputs
 // loaded a chunk ahead), then the column levels with the rings loaded from,
 // and at the end saved to, the resident state. The state is kept in absolute
@@ -24,11 +24,11 @@
 namespace swdft {
 namespace tree {
 
-// Lanes per column stream: two from n0 = 8 on (as the single-image kernel's
-// split streams), which doubles the strips of a call and halves each lane's
-// column work per row; calls are short, so their time is set by how long one
-// wave takes for its rows.
-constexpr int stream_kg(int n0) { return n0 >= 8 ? 2 : 1; }
+// Lanes per column stream: two from n0 = 4 on (the split of the single-image
+// kernel), which doubles the strips of a call and halves each lane's column
+// work per row; calls are short, so their time is set by how long one wave
+// takes for its rows.
+constexpr int stream_kg(int n0) { return n0 >= 4 ? 2 : 1; }
 
 template <int N0W, int N1W, bool REAL>
 __global__ __launch_bounds__(64) void tree_stream_kernel(const void* __restrict__ xv,
