@@ -34,6 +34,7 @@ import json
 import os
 import sys
 import time
+import statistics
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -192,11 +193,17 @@ def time_batch(fn, steps: int, stream) -> float:
     return start.elapsed_time(end) / steps
 
 
-def roofline(alg_bytes: int, avg_ms: float, kernel: str, traffic=None) -> dict:
+def roofline(alg_bytes: int, avg_ms: float, kernel: str, traffic=None, med_ms=None) -> dict:
+    """`achieved` uses the mean launch duration; the median is reported beside
+    it (and the fraction it gives)."""
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
-    return {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": kernel,
-            "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_us": avg_ms * 1e3}
+    out = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": kernel,
+           "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_us": avg_ms * 1e3}
+    if med_ms is not None:
+        out["median_launch_us"] = med_ms * 1e3
+        out["median_frac"] = alg_bytes / (med_ms * 1e-3) / 1e9 / PEAK_HBM_GBS
+    return out
 
 
 def oracle_rate(orc, x2d, n0, n1, P0, P1, seconds: float, seed: int):
@@ -239,14 +246,15 @@ def base_record(args, value, ms_per_step, dtype, config) -> dict:
 
 
 def forward_leg(plan, x, args, stream):
-    """Warm up and time `plan.forward`; returns (y, avg_ms, wall_per_step_s)."""
+    """Warm up and time `plan.forward`; returns (y, avg_ms, wall_per_step_s,
+    median_ms)."""
     import torch
     y = torch.empty(plan.out_shape, dtype=plan.out_dtype, device=x.device)
     for _ in range(args.warmup):
         plan.forward(x, out=y)
     torch.cuda.synchronize()
-    avg_ms, wall, _ = time_launches(lambda: plan.forward(x, out=y), args.steps, stream)
-    return y, avg_ms, wall / args.steps
+    avg_ms, wall, durs = time_launches(lambda: plan.forward(x, out=y), args.steps, stream)
+    return y, avg_ms, wall / args.steps, statistics.median(durs)
 
 
 def sampled(y_img, q0, q1):
@@ -284,8 +292,8 @@ def run_sin1024(args, swd, dev) -> dict:
         torch.cuda.synchronize()
         log(f"copy calibration: 3 copies of {src.numel() * 4} bytes")
         del src, dst
-    y, avg_ms, step_s = forward_leg(plan, x, args, stream)
-    rf = roofline(alg_bytes, avg_ms, "tree_fwd_kernel<16,16,real>", measured_traffic())
+    y, avg_ms, step_s, med_ms = forward_leg(plan, x, args, stream)
+    rf = roofline(alg_bytes, avg_ms, "tree_fwd_kernel<16,16,real>", measured_traffic(), med_ms)
     log(f"tree: {avg_ms * 1e3:.1f} us/launch, {rf['achieved']:.0f} GB/s")
     q0, q1 = workloads.window_sample(P0, P1, 4096, 2002)
     got = sampled(y[0], q0, q1)
@@ -353,8 +361,8 @@ def run_cplx2048(args, swd, dev) -> dict:
     alg_bytes = plan.output_bytes() + x.numel() * 8
     stream = torch.cuda.current_stream(dev)
     log(plan.describe())
-    y, avg_ms, step_s = forward_leg(plan, x, args, stream)
-    rf = roofline(alg_bytes, avg_ms, "tree_fwd_kernel<32,8,complex>")
+    y, avg_ms, step_s, med_ms = forward_leg(plan, x, args, stream)
+    rf = roofline(alg_bytes, avg_ms, "tree_fwd_kernel<32,8,complex>", med_ms=med_ms)
     log(f"tree: {avg_ms * 1e3:.1f} us/launch, {rf['achieved']:.0f} GB/s")
     q0, q1 = workloads.window_sample(P0, P1, 4096, 2003)
     got = sampled(y[0], q0, q1)
@@ -412,8 +420,8 @@ def run_mixed1024(args, swd, dev) -> dict:
     coeffs = plan.output_elems()
     alg_bytes = plan.output_bytes() + x.numel() * 4
     log(plan.describe())
-    y, avg_ms, step_s = forward_leg(plan, x, args, stream)
-    rf = roofline(alg_bytes, avg_ms, f"tree_mixed_kernel<{n0},{n1},real>")
+    y, avg_ms, step_s, med_ms = forward_leg(plan, x, args, stream)
+    rf = roofline(alg_bytes, avg_ms, f"tree_mixed_kernel<{n0},{n1},real>", med_ms=med_ms)
     log(f"mixed tree {n0}x{n1}: {avg_ms * 1e3:.1f} us/launch, {rf['achieved']:.0f} GB/s")
     q0, q1 = workloads.window_sample(P0, P1, 4096, 2008)
     got = sampled(y[0], q0, q1)
@@ -436,7 +444,7 @@ def run_mixed1024(args, swd, dev) -> dict:
     extra = []
     for (m0, m1) in ((9, 9), (24, 24), (12, 16)):
         pe = swd.Plan(N0, N1, m0, m1, torch.float32, batch=1)
-        _, e_ms, _ = forward_leg(pe, x, args, stream)
+        _, e_ms, _, _ = forward_leg(pe, x, args, stream)
         eb = pe.output_bytes() + x.numel() * 4
         extra.append({"n0": m0, "n1": m1, "avg_launch_us": e_ms * 1e3,
                       "coeffs_per_s": pe.output_elems() / (e_ms * 1e-3),
@@ -497,8 +505,8 @@ def run_vol128(args, swd, dev) -> dict:
     alg_bytes = coeffs * 8 + x.numel() * 4
     stream = torch.cuda.current_stream(dev)
     log(plan.describe())
-    y, avg_ms, step_s = forward_leg(plan, x, args, stream)
-    rf = roofline(alg_bytes, avg_ms, "tree3_fwd_kernel<8,8,8,real>")
+    y, avg_ms, step_s, med_ms = forward_leg(plan, x, args, stream)
+    rf = roofline(alg_bytes, avg_ms, "tree3_fwd_kernel<8,8,8,real>", med_ms=med_ms)
     log(f"tree3d: {avg_ms * 1e3:.1f} us/launch, {rf['achieved']:.0f} GB/s")
     q = workloads.window_sample3(P, 256, 3006)
     got = y[0][tuple(torch.from_numpy(a).to(dev) for a in q)].cpu().numpy()
@@ -624,7 +632,7 @@ def run_grad256(args, swd, dev) -> dict:
     coeffs = plan.output_elems()
     stream = torch.cuda.current_stream(dev)
     log(plan.describe())
-    y, f_ms, f_step = forward_leg(plan, x, args, stream)
+    y, f_ms, f_step, f_med = forward_leg(plan, x, args, stream)
     dy = 2.0 * w * y
     dx = torch.empty_like(x)
     for _ in range(args.warmup):
@@ -632,7 +640,8 @@ def run_grad256(args, swd, dev) -> dict:
     torch.cuda.synchronize()
     b_ms, b_wall, _ = time_launches(lambda: plan.backward(dy, out=dx), args.steps, stream)
     b_step = b_wall / args.steps
-    rf_f = roofline(plan.output_bytes() + x.numel() * 4, f_ms, "tree_fwd_kernel<16,16,real>")
+    rf_f = roofline(plan.output_bytes() + x.numel() * 4, f_ms, "tree_fwd_kernel<16,16,real>",
+                    med_ms=f_med)
     rf_b = roofline(plan.output_bytes() + x.numel() * 4, b_ms,
                     "tree_adj_kernel<16,16,real> + reduce")
     log(f"fwd {f_ms * 1e3:.1f} us, bwd {b_ms * 1e3:.1f} us ({rf_b['achieved']:.0f} GB/s)")

@@ -3,7 +3,7 @@
  *
  * Problem (Sec. 4.1, Eq. (2)): for an N0 x N1 array x and radix-2 windows
  * n0 = 2^m0, n1 = 2^m1 (n_i <= N_i, non-square allowed), or mixed-radix
- * windows whose sides are 2^a 3^b (Sec. 6; see swdft2d_plan), compute for
+ * windows whose sides are 2^a 3^b (Sec. 5; see swdft2d_plan), compute for
  * every window position the 2D DFT of that n0 x n1 window:
  *
  *   y[b][q0][q1][k0][k1] = s * sum_{j0<n0} sum_{j1<n1} x[b][q0+j0][q1+j1]
@@ -50,12 +50,31 @@
  * Streams: exec and backward only enqueue work on the given stream (0 = the
  * null stream) and never synchronise. The caller must not destroy a plan, nor
  * free its buffers, while work enqueued with it is in flight. Calls with one
- * plan from several host threads must be serialised by the caller.
+ * plan from several host threads must be serialised by the caller. All
+ * swdft2d_backward calls of one plan share its one workspace: calls on
+ * different streams must be ordered by the caller (events), or each stream
+ * should use a plan of its own.
  *
  * Errors: every entry point returns a status and never aborts. All argument
  * checks happen on the host before anything is enqueued; on an error nothing
  * is enqueued and outputs are untouched. swdft2d_last_error() gives a
  * thread-local detail string for the last failing call on this thread.
+ *
+ * Environment variables read by the library. None changes what is computed;
+ * the SWDFT_*_SLAB / TREE_* ones change only the launch shape (and so, for
+ * the tree, nothing but the order of independent work), and are read each
+ * time a plan derives its launch shape (at every exec). A value the shape
+ * has no kernel for falls back to the default; a plan's own tuned choice
+ * (swdft2d_tune or the cache) takes precedence over them.
+ *   SWDFT_AUTOTUNE_CACHE  path of the JSON-lines tuning cache (swdft2d_tune)
+ *   SWDFT_TREE_KG         lanes per column stream of the forward tree (1 or 2;
+ *                         n0 = 64 plans have one split per n1)
+ *   SWDFT_TREE_WPC        resident workgroups per CU of the forward tree
+ *                         (0 = no cap, 1..8)
+ *   SWDFT_TREE_WV         waves per strip of the forward tree (1 or 2)
+ *   SWDFT_TREE_SLAB       window rows per workgroup of the forward tree
+ *   SWDFT_ADJ_SLAB        dx rows per workgroup of swdft2d_backward
+ *   SWDFT_DENSE_SLAB      window rows per workgroup of DENSE_BF16X2
  */
 #ifndef SWDFT2D_H
 #define SWDFT2D_H
@@ -212,6 +231,16 @@ swdft_status_t swdft2d_plan_batched(swdft2d_plan_t* out, const swdft2d_desc_t* d
  * exec. R64/C64 plans have nothing to tune (returns SWDFT_OK). */
 swdft_status_t swdft2d_tune(swdft2d_plan_t plan, const void* x, void* y, hipStream_t stream);
 
+/* Copy the plan's FP32 twiddle vector of one axis (Sec. 4.2: Omega^0 for
+ * axis 0, length n0; Omega^1 for axis 1, length n1) into out as interleaved
+ * (re, im) floats, out[2m] + i out[2m+1] = Omega[m] = exp(-2 pi i m / n)
+ * generated in FP64 and rounded once to nearest-even: exactly 1 at m = 0, -i
+ * at m = n/4, and Omega[m + n/2] = -Omega[m] for even n. These are the values
+ * every FP32 kernel of the plan multiplies by. Read-only; touches no GPU.
+ * Checks: live single-image plan (E_PLAN); axis 0 or 1, out != NULL and
+ * len >= 2 n (E_ARG). */
+swdft_status_t swdft2d_twiddles(swdft2d_plan_t plan, int32_t axis, float* out, int32_t len);
+
 /* Measurement aid (not part of the transform): fill `bytes` bytes at y
  * (8-byte aligned, bytes a multiple of 8) with a constant, with the access
  * pattern of a device memset (16-byte stores, 256 workgroups sweeping the
@@ -266,7 +295,7 @@ swdft_status_t swdft2d_stream_reset(swdft2d_stream_t s, hipStream_t stream);
  * accepted). The caller must not destroy it while its work is in flight. */
 swdft_status_t swdft2d_stream_destroy(swdft2d_stream_t s);
 
-/* ---- 3D sliding-window DFT: the k-dimensional extension of Sec. 4.8 with
+/* ---- 3D sliding-window DFT: the k-dimensional extension of Sec. 4.4 with
  * k = 3. Its trees run the levels of axis 2, then axis 1, then axis 0 (the
  * three instances of Eq. (7) printed there) and end in the 3D DFT of every
  * window:

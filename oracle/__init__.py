@@ -6,7 +6,7 @@ this package. The GPU library never does, and the two share no code.
 
 The arithmetic lives in ``oracle.c`` (plain C, FP64, the definition of
 Eq. (2) of Sec. 4.1 evaluated window by window, its explicit adjoint, and the
-3D definition that the trees of Sec. 4.8 reach). This
+3D definition that the trees of Sec. 4.4 reach). This
 wrapper only marshals numpy arrays and compiles the C file with gcc when the
 shared object is missing or older than its source.
 """

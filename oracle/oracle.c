@@ -1,6 +1,6 @@
 /*
  * FP64 oracle for the 2D sliding-window DFT (2D SWDFT), and for its 3D
- * extension (Sec. 4.8).
+ * extension (Sec. 4.4).
  *
  * TEST INFRASTRUCTURE. Only the test suite, the smoke check and the bench's
  * CPU-baseline leg may load this code; the product path never does. It shares
@@ -234,7 +234,7 @@ int oracle_swdft2d_adjoint(const double* dy_re, const double* dy_im, int64_t N0,
 
 /*
  * Forward 3D SWDFT at a list of windows: the k-dimensional extension of
- * Sec. 4.8 (Eq. (7) and its three-dimensional instances), whose trees end in
+ * Sec. 4.4 (Eq. (7) and its three-dimensional instances), whose trees end in
  * the plain 3D DFT of every window:
  *
  *   a[q0][q1][q2][k0][k1][k2] = s * sum_{j0<n0} sum_{j1<n1} sum_{j2<n2}

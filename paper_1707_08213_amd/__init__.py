@@ -252,7 +252,12 @@ _plan_cache: dict = {}
 
 
 def _cached_plan(N0, N1, n0, n1, dtype, batch, norm, algo) -> Plan:
-    key = (N0, N1, n0, n1, dtype, batch, norm, algo)
+    # A plan holds one adjoint workspace and its calls must not overlap, so
+    # plans are cached per host thread and per device stream: calls on one
+    # (thread, stream) pair are ordered by that stream.
+    stream = torch.cuda.current_stream().cuda_stream if torch.cuda.is_available() else 0
+    key = (N0, N1, n0, n1, dtype, batch, norm, algo, threading.get_ident(),
+           torch.cuda.current_device() if torch.cuda.is_available() else -1, stream)
     with _cache_lock:
         p = _plan_cache.get(key)
         if p is None:
@@ -279,7 +284,7 @@ def swdft2d(x: torch.Tensor, n0: int, n1: int, norm: str = "none", algo: str = "
 
 class Plan3D:
     """One swdft3d plan: `batch` volumes of N0 x N1 x N2, n0 x n1 x n2 windows
-    (the 3D extension of Sec. 4.8)."""
+    (the 3D extension of Sec. 4.4)."""
 
     def __init__(self, N0, N1, N2, n0, n1, n2, dtype=torch.float32, batch=1, norm="none"):
         if dtype not in (torch.float32, torch.complex64):
@@ -408,7 +413,13 @@ def swdft3d(x: torch.Tensor, n0: int, n1: int, n2: int, norm: str = "none") -> t
     squeeze = x.dim() == 3
     xb = x.unsqueeze(0) if squeeze else x
     B, N0, N1, N2 = xb.shape
-    y = Plan3D(N0, N1, N2, n0, n1, n2, dtype=xb.dtype, batch=B, norm=norm).forward(xb)
+    key = ("3d", N0, N1, N2, n0, n1, n2, xb.dtype, B, norm)
+    with _cache_lock:
+        p = _plan_cache.get(key)
+        if p is None:
+            p = Plan3D(N0, N1, N2, n0, n1, n2, dtype=xb.dtype, batch=B, norm=norm)
+            _plan_cache[key] = p
+    y = p.forward(xb)
     return y[0] if squeeze else y
 
 

@@ -23,7 +23,6 @@ STATUS = {
     8: "SWDFT_E_DEVICE", 9: "SWDFT_E_PLAN",
 }
 STATUS_CODE = {v: k for k, v in STATUS.items()}
-MAX_WINDOW = 32
 
 class Desc(ctypes.Structure):
     """swdft2d_desc_t"""
@@ -47,6 +46,7 @@ SIGNATURES = {
     "swdft2d_status_string": (ctypes.c_char_p, [_int]),
     "swdft2d_last_error": (ctypes.c_char_p, []),
     "swdft2d_write_probe": (_int, [_vp, _i64, _vp]),
+    "swdft2d_twiddles": (_int, [_vp, _i32, ctypes.POINTER(ctypes.c_float), _i32]),
     "swdft2d_plan_batched": (_int, [_PLAN_P, _vp, _i64, _int]),
     "swdft2d_tune": (_int, [_vp, _vp, _vp, _vp]),
     "swdft2d_stream_create": (_int, [_PLAN_P, _i64, _i32, _i32, _int]),

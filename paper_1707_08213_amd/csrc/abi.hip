@@ -437,7 +437,10 @@ swdft_status_t swdft2d_backward(swdft2d_plan_t plan, const void* dy, void* dx, h
   swdft_status_t st = check_buffers(p, dy, y_elem_bytes(p->dtype), yb, dx,
                                     x_elem_bytes(p->dtype), xb, "dy", "dx");
   if (st != SWDFT_OK) return st;
-  if (resolve_algo(p) != SWDFT_ALGO_TREE)
+  // The adjoint is always the transposed tree, whichever forward kernel an
+  // AUTO plan ends up running (the tuner may pick the dense variant for the
+  // forward transform; the adjoint of the map x -> y is the same).
+  if (f64_dtype(p->dtype) || (p->algo != SWDFT_ALGO_AUTO && p->algo != SWDFT_ALGO_TREE))
     return fail(SWDFT_E_DTYPE, "backward runs the transposed tree; it needs an R32/C32 plan "
                 "with the TREE (or AUTO) algorithm");
   const swdft::AdjGeom g = adj_geom(p);
@@ -449,6 +452,21 @@ swdft_status_t swdft2d_backward(swdft2d_plan_t plan, const void* dy, void* dx, h
                                         static_cast<const float2*>(dy), p->workspace, dx, g,
                                         p->tw32, stream);
   if (e != hipSuccess) return device_fail(e, "adjoint launch");
+  return SWDFT_OK;
+}
+
+swdft_status_t swdft2d_twiddles(swdft2d_plan_t plan, int32_t axis, float* out, int32_t len) {
+  if (!is_live(plan)) return fail(SWDFT_E_PLAN, "null or destroyed plan");
+  if (plan->kind != 0) return fail(SWDFT_E_PLAN, "a batched plan has one twiddle table per shape");
+  if (axis != 0 && axis != 1) return fail(SWDFT_E_ARG, "axis must be 0 or 1, not %d", axis);
+  const int n = axis == 0 ? plan->n0 : plan->n1;
+  if (out == nullptr || len < 2 * n)
+    return fail(SWDFT_E_ARG, "twiddle output needs %d floats", 2 * n);
+  const float2* w = axis == 0 ? plan->tw32.w0 : plan->tw32.w1;
+  for (int m = 0; m < n; ++m) {
+    out[2 * m] = w[m].x;
+    out[2 * m + 1] = w[m].y;
+  }
   return SWDFT_OK;
 }
 

@@ -1,5 +1,5 @@
 // C ABI of the 3D sliding-window DFT (the k-dimensional extension of
-// Sec. 4.8, k = 3): plan validation, launch shape and dispatch.
+// Sec. 4.4, k = 3): plan validation, launch shape and dispatch.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>

@@ -1,5 +1,5 @@
 // Fused forward 3D Tree SWDFT for gfx950 (the k-dimensional extension of
-// Sec. 4.8, k = 3).
+// Sec. 4.4, k = 3).
 //
 // The trees of the 3D extension run m2 levels along axis 2, then m1 along
 // axis 1, then m0 along axis 0 (the three level equations that instantiate

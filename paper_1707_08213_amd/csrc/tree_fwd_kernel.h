@@ -85,6 +85,17 @@ __device__ __forceinline__ float2 uload(const float2* p) {
   return make_float2(q[0], q[1]);
 }
 
+// A 64-bit value known to be the same in every lane, kept in scalar registers.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
 template <typename T>
 __device__ __forceinline__ T uniform_copy(const T& src) {
   static_assert(sizeof(T) % 4 == 0, "dword-sized");
@@ -396,12 +407,12 @@ __device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float
   const int cp_res = (lane / N1W) % KG + KG * wv;
   const int cp_k1 = lane % N1W;
   // Output of one row of the strip: QW windows of n0*n1 values from ystrip +
-  // q0 * y_row_stride; only the first strip_bytes exist (the last strip of a
+  // q0 * row_bytes; only the first strip_bytes exist (the last strip of a
   // row may be partial).
   float2* ystrip = yimg + q1_0 * (N0W * N1W);
-  const int64_t y_row_stride = g.P1 * (N0W * N1W);
-  const uint32_t strip_bytes =
-      (uint32_t)(min((int64_t)C::QW, g.P1 - q1_0) * (N0W * N1W * (int)sizeof(float2)));
+  const uint64_t row_bytes = (uint64_t)g.P1 * (N0W * N1W * sizeof(float2));
+  const uint32_t strip_bytes = uniform_u32(
+      (uint32_t)(min((int64_t)C::QW, g.P1 - q1_0) * (N0W * N1W * (int)sizeof(float2))));
   const uint32_t lane_off =
       (uint32_t)((cp_c * (N0W * N1W) + cp_res * N1W + cp_k1) * (int)sizeof(float2));
 
@@ -471,16 +482,29 @@ __device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float
     const float2* zcol = zl + cp_c * C::ZS + cp_k1;
     float2 zq[C::CR];
     sfor<0, (kLdsAhead < C::CR ? kLdsAhead : C::CR)>([&](auto K) { zq[K] = zcol[K * C::ZROW]; });
+    // Step st writes window row q0 = crow + st - (n0 - 1) when row0 <= q0 <
+    // q0_end, i.e. for st in [st_lo, st_hi); the other steps prime the rings
+    // (or run past the slab) and get an empty resource. The row's address is
+    // kept as a running scalar value, so a step spends a handful of scalar
+    // instructions on its resource (a wave's instruction issue bounds the
+    // tile: a 64-bit multiply and compare per row cost about 8% of the rate).
+    const int st_lo = (int)uniform_u32(
+        (uint32_t)max<int64_t>(0, min<int64_t>(row0 + (N0W - 1) - crow, C::CR)));
+    const int st_hi = (int)uniform_u32(
+        (uint32_t)max<int64_t>(st_lo, min<int64_t>(q0_end + (N0W - 1) - crow, C::CR)));
+    const uint32_t st_span = (uint32_t)(st_hi - st_lo);
+    // address of row crow - (n0 - 1), as an integer: the first rows of the
+    // top slab lie before y and are never written
+    uint64_t row_addr = uniform_u64((uint64_t)(uintptr_t)ystrip +
+                                    (uint64_t)(crow - (N0W - 1)) * row_bytes);
     sfor<0, C::CR>([&](auto STc) {
       constexpr int st = STc;
       if constexpr (st + kLdsAhead < C::CR) zq[st + kLdsAhead] = zcol[(st + kLdsAhead) * C::ZROW];
       __builtin_amdgcn_sched_barrier(0);  // keep the read ahead of this step's work
       const float2 z = zq[st];
-      const int64_t q0 = crow + st - (N0W - 1);
-      // priming rows (and rows past the slab) get an empty resource
-      const bool row_store = (q0 >= row0) && (q0 < q0_end);
-      const auto out = buf_rsrc(ystrip + (row_store ? q0 : 0) * y_row_stride,
-                                row_store ? strip_bytes : 0u);
+      const uint32_t nbytes = uniform_u32((uint32_t)(st - st_lo) < st_span ? strip_bytes : 0u);
+      const auto out = buf_rsrc((const void*)(uintptr_t)uniform_u64(row_addr), nbytes);
+      row_addr += row_bytes;
       if constexpr (N0W == 1) {
         store_buf<C::NT_STORES>(out, lane_off, z);
       } else {

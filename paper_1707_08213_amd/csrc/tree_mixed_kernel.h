@@ -1,6 +1,6 @@
 // Mixed-radix fused forward 2D Tree SWDFT for gfx950: window sides of the
 // form 2^a 3^b. The tree of Sec. 4.2 is binary because the FFT it follows is
-// radix-2; a radix-3 factor turns a level into ternary trees (Sec. 6), and a
+// radix-2; a radix-3 factor turns a level into ternary trees (Sec. 5), and a
 // side such as 12 = 2 * 2 * 3 mixes both.
 //
 // Levels. A side n = r_1 r_2 ... r_m is factored with the twos first, then

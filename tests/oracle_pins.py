@@ -12,7 +12,7 @@ disagrees with:
     windows that recursive sliding DFTs are built on (Sec. 2), linearity),
   * the adjoint identities (dot-product test, exact central differences of a
     quadratic loss),
-  * for the 3D extension (Sec. 4.8): numpy.fft.fftn per window, separable
+  * for the 3D extension (Sec. 4.4): numpy.fft.fftn per window, separable
     inputs against 1D sliding DFTs, exact Gaussian integers, the sliding
     recurrence along the last axis, Parseval and the orthonormal scale.
 
@@ -66,7 +66,7 @@ def pin_fft2(orc):
 
 def pin_mixed_radix(orc):
     """Windows that are not powers of two (the radix-3 and mixed 2/3 trees of
-    Sec. 6): each window equals numpy.fft.fft2 of that window, the twiddle of
+    Sec. 5): each window equals numpy.fft.fft2 of that window, the twiddle of
     a third of a turn is exp(-2 pi i / 3) (checked through an on-bin
     exponential), and Parseval holds per window."""
     rng = np.random.default_rng(14)
@@ -312,7 +312,7 @@ def pin_quadratic_fd(orc):
         assert abs(fd - grad[r, c]) < 1e-10 * max(1.0, abs(fd)), (r, c, fd, grad[r, c])
 
 
-# ---- 3D SWDFT (the k-dimensional extension of Sec. 4.8, k = 3)
+# ---- 3D SWDFT (the k-dimensional extension of Sec. 4.4, k = 3)
 
 def pin3d_fftn(orc):
     """Each 3D window equals numpy.fft.fftn of that window (real and complex

@@ -429,3 +429,80 @@ def test_mixed_radix_launch_rules(n0, n1, slabs, waves):
     d = buf.value.decode()
     assert f" slabs={slabs} " in d and f" waves={waves} " in d, d
     lib.swdft2d_destroy(h)
+
+
+def _plan_twiddles(n0, n1):
+    st, h = make_plan(max(n0, n1) + 8, max(n0, n1) + 8, n0, n1)
+    assert st == S["SWDFT_OK"]
+    try:
+        out = []
+        for axis, n in ((0, n0), (1, n1)):
+            buf = (ctypes.c_float * (2 * n))()
+            assert lib.swdft2d_twiddles(h, axis, buf, 2 * n) == S["SWDFT_OK"]
+            out.append([(buf[2 * m], buf[2 * m + 1]) for m in range(n)])
+        return out
+    finally:
+        lib.swdft2d_destroy(h)
+
+
+def _rn_even_f32(exact):
+    """Round an exact rational to the nearest float32, ties to even."""
+    import numpy as np
+    from fractions import Fraction
+    f = np.float32(float(exact))
+    best = None
+    for c in (np.nextafter(f, np.float32(-np.inf)), f, np.nextafter(f, np.float32(np.inf))):
+        d = abs(Fraction(float(c)) - exact)
+        even = (int(np.array(c, dtype=np.float32).view(np.uint32)) & 1) == 0
+        key = (d, not even)
+        if best is None or key < best[0]:
+            best = (key, c)
+    return float(best[1])
+
+
+@pytest.mark.parametrize("n", [1, 2, 4, 8, 16, 32, 64, 3, 6, 9, 12, 24])
+def test_fp32_twiddle_table(n):
+    """Sec. 4.2's twiddle vectors as the kernels receive them: every entry is
+    exp(-2 pi i m / n) rounded once to nearest-even FP32 (the exact value
+    from 60-digit mpmath, rounded exactly here), 1 at m = 0 and -i at n/4
+    exactly, and Omega[m + n/2] = -Omega[m] bit for bit for even n."""
+    import struct
+    from fractions import Fraction
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 60
+    partner = 4 if n in (3, 6, 9, 12, 24) else n
+    w0, w1 = _plan_twiddles(n, partner)
+    w0b, w1b = _plan_twiddles(partner, n)
+    assert w0 == w1b and w1 == w0b  # the same table on either axis
+    table = w0
+
+    def exact(v):  # 60 significant digits, far finer than any FP32 rounding boundary
+        return Fraction(mpmath.nstr(v, 60, strip_zeros=False))
+
+    for m in range(n):
+        ang = -2 * mpmath.pi * m / n
+        want = (_rn_even_f32(exact(mpmath.cos(ang))), _rn_even_f32(exact(mpmath.sin(ang))))
+        assert table[m] == want, (n, m, table[m], want)
+    assert table[0] == (1.0, 0.0)
+    if n % 4 == 0:
+        assert table[n // 4] == (0.0, -1.0)
+        assert table[n // 2] == (-1.0, 0.0) and table[3 * n // 4] == (0.0, 1.0)
+    if n % 2 == 0:
+        bits = lambda v: struct.pack("<ff", *v)  # noqa: E731
+        for m in range(n // 2):
+            neg = (-table[m][0], -table[m][1])
+            assert bits(table[m + n // 2]) == bits(neg), (n, m)
+
+
+def test_twiddles_argument_checks():
+    st, h = make_plan(40, 40, 8, 16)
+    assert st == S["SWDFT_OK"]
+    try:
+        buf = (ctypes.c_float * 64)()
+        assert lib.swdft2d_twiddles(h, 2, buf, 64) == S["SWDFT_E_ARG"]
+        assert lib.swdft2d_twiddles(h, 1, buf, 31) == S["SWDFT_E_ARG"]
+        assert lib.swdft2d_twiddles(h, 0, None, 64) == S["SWDFT_E_ARG"]
+        assert lib.swdft2d_twiddles(h, 1, buf, 32) == S["SWDFT_OK"]
+    finally:
+        lib.swdft2d_destroy(h)
+    assert lib.swdft2d_twiddles(None, 0, buf, 64) == S["SWDFT_E_PLAN"]

@@ -1,4 +1,4 @@
-"""Parity of the 3D tree (the k-dimensional extension of Sec. 4.8, k = 3)
+"""Parity of the 3D tree (the k-dimensional extension of Sec. 4.4, k = 3)
 against the FP64 oracle, through the C ABI.
 
 Tolerance: normwise relative max error <= 1e-5 (as for the 2D tree; the

@@ -184,3 +184,36 @@ def test_backward_rejects_direct_plan(swd):
     with pytest.raises(swd.SwdftError) as e:
         p.backward(dy)
     assert e.value.name == "SWDFT_E_DTYPE"
+
+
+def test_backward_after_dense_tuning(swd, orc, tmp_path, monkeypatch):
+    """A tuning-cache line that picks the dense variant for the forward pass
+    of an AUTO plan must leave the adjoint (always the transposed tree)
+    usable: forward through the dense kernel, then autograd's backward, both
+    against the oracle (forward: the dense tolerance; gradient: the oracle's
+    explicit adjoint of the same dy)."""
+    N0, N1, n0, n1 = 41, 53, 16, 16
+    P0, P1 = N0 - n0 + 1, N1 - n1 + 1
+    size = int(P0 * P1).bit_length() - 1
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    cache = tmp_path / "tune.jsonl"
+    cache.write_text('{"arch":"%s","kind":"single","n0":%d,"n1":%d,"real":1,"size":%d,'
+                     '"algo":"dense","kg":1,"slab":0,"wpc":-1,"wv":0,"us":1.0}\n'
+                     % (arch, n0, n1, size))
+    monkeypatch.setenv("SWDFT_AUTOTUNE_CACHE", str(cache))
+    rng = np.random.default_rng(21)
+    x_np = rng.standard_normal((N0, N1)).astype(np.float32)
+    x = torch.from_numpy(x_np).cuda().requires_grad_(True)
+    print("[case] forward (dense from the tuning cache) then backward", flush=True)
+    A = swd.SWDFT2dFn.apply(x, n0, n1)
+    g_np = (rng.standard_normal((P0, P1, n0, n1)) +
+            1j * rng.standard_normal((P0, P1, n0, n1))).astype(np.complex64)
+    g = torch.from_numpy(g_np).cuda()
+    (A * g.conj()).real.sum().backward()
+    torch.cuda.synchronize()
+    plan = swd._cached_plan(N0, N1, n0, n1, torch.float32, 1, "none", "auto")
+    assert "dense" in plan.describe(), plan.describe()
+    A_ref = orc.swdft2d(x_np.astype(np.float64), n0, n1)
+    assert rel_err(A.detach().cpu().numpy(), A_ref) <= 5e-5
+    grad_ref = orc.swdft2d_adjoint(g_np.astype(np.complex128), N0, N1).real
+    assert rel_err(x.grad.cpu().numpy(), grad_ref) <= TOL

@@ -1,5 +1,5 @@
 """Parity of the mixed-radix tree (window sides 2^a 3^b, the radix-3 and
-mixed trees of Sec. 6) and of the FP64 direct kernel on such windows, against
+mixed trees of Sec. 5) and of the FP64 direct kernel on such windows, against
 the FP64 oracle, through the C ABI.
 
 Tolerance: normwise relative max error <= 1e-5 for the FP32 tree, <= 1e-12

@@ -170,7 +170,7 @@ def uneven64(seed: int = WORKLOAD_SEEDS["uneven64"], count: int = 64,
 
 def vol128(seed: int = WORKLOAD_SEEDS["vol128"], N: int = 128, n: int = 8):
     """One N x N x N real FP32 volume, N(0,1), with n x n x n windows (the 3D
-    extension of Sec. 4.8): 121^3 windows of 512 coefficients at the defaults."""
+    extension of Sec. 4.4): 121^3 windows of 512 coefficients at the defaults."""
     return dict(x=normal_real((N, N, N), seed), n=(n, n, n))
 
 
