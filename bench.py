@@ -135,6 +135,44 @@ def pmc_summary(fetch_db: str, write_db: str, copy_bytes: int, out_json: str) ->
     return "\n".join(lines)
 
 
+def counter_summary(db: str) -> str:
+    """Per-kernel means of every counter in a rocprofv3 --pmc database
+    (markdown), and each SQ_INSTS_* / SQ_WAIT_* counter divided by SQ_WAVES
+    when that counter was collected (per-wave figures)."""
+    import collections
+    import sqlite3
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    con = sqlite3.connect(db)
+    for name, counter, v in con.execute(
+            "select kernel_name, counter_name, value from counters_collection"):
+        short = name.replace("(anonymous namespace)", "anon").split("(")[0].replace("void ", "")
+        vals[short][counter].append(float(v))
+    con.close()
+    counters = sorted({c for d in vals.values() for c in d})
+    lines = ["| kernel | dispatches | " + " | ".join(counters) + " |",
+             "|---|---|" + "---|" * len(counters)]
+    per_wave = []
+    for name, d in sorted(vals.items()):
+        n = max(len(v) for v in d.values())
+        means = {c: sum(d[c]) / len(d[c]) for c in counters if d.get(c)}
+        lines.append(f"| {name[:70]} | {n} | " +
+                     " | ".join(f"{means[c]:.4g}" if c in means else "" for c in counters) + " |")
+        if means.get("SQ_WAVES"):
+            w = means["SQ_WAVES"]
+            per_wave.append((name, w, {c: means[c] / w for c in means
+                                       if c.startswith(("SQ_INSTS", "SQ_WAIT", "SQ_WAVE_CYCLES",
+                                                        "SQ_BUSY"))}))
+    if per_wave:
+        cols = sorted({c for _, _, d in per_wave for c in d})
+        lines += ["", "Per wave (counter / SQ_WAVES):", "",
+                  "| kernel | waves | " + " | ".join(cols) + " |",
+                  "|---|---|" + "---|" * len(cols)]
+        for name, w, d in per_wave:
+            lines.append(f"| {name[:70]} | {w:.0f} | " +
+                         " | ".join(f"{d[c]:.4g}" if c in d else "" for c in cols) + " |")
+    return "\n".join(lines)
+
+
 def trace_summary(db: str) -> str:
     """Per-kernel duration table (markdown) from a rocprofv3 --kernel-trace
     database, one row per kernel and grid size."""
@@ -381,6 +419,21 @@ def run_cplx2048(args, swd, dev) -> dict:
              "roofline": roofline(alg_bytes, d_ms, "dense_fwd_kernel<32,8,complex>"),
              "mfma_tflops": d_flops / (d_ms * 1e-3) / 1e12, "mfma_peak_tflops": 2500.0}
     log(f"dense: {d_ms * 1e3:.1f} us/launch")
+    # the adjoint (transposed tree) of the same plan: reads dy (the layout of
+    # y; here the dense output), writes dx
+    dx = torch.empty_like(x)
+    for _ in range(args.warmup):
+        plan.backward(y, out=dx)
+    torch.cuda.synchronize()
+    a_ms, _, a_durs = time_launches(lambda: plan.backward(y, out=dx), args.steps, stream)
+    adj = {"roofline": roofline(plan.output_bytes() + x.numel() * 8, a_ms,
+                                "tree_adj_kernel<32,8,complex> + reduce",
+                                med_ms=statistics.median(a_durs)),
+           "avg_launch_us": a_ms * 1e3}
+    log(f"adjoint: {a_ms * 1e3:.1f} us/launch ({adj['roofline']['achieved']:.0f} GB/s)")
+    pr, pc = workloads.pixel_sample(N0, N1, 256, 57)
+    dx_s = dx[0].cpu().numpy()[pr, pc]
+    dy_np = y[0].cpu().numpy() if not args.no_cpu_baseline else None
     del y
     cpu, err = None, None
     if not args.no_cpu_baseline:
@@ -392,12 +445,15 @@ def run_cplx2048(args, swd, dev) -> dict:
         dense["rel_err"] = rel(got_d, ref)
         dense["max_abs_err"] = float(np.max(np.abs(got_d - ref)))
         cpu = oracle_rate(orc, xd, n0, n1, P0, P1, args.cpu_seconds, 3003)
+        adj_ref = orc.swdft2d_adjoint(dy_np.astype(np.complex128), N0, N1, pixels=(pr, pc))
+        adj["rel_err"] = rel(dx_s, adj_ref)
     out = base_record(args, coeffs / step_s, step_s * 1e3, "f32", {
         "workload": "cplx2048: one 2048x512 complex64 image (re, im N(0,1)), 32x8 windows -> "
                     "2017x505x256 complex64 coefficients",
         "N0": N0, "N1": N1, "n0": n0, "n1": n1, "batch": 1, "algo": "tree",
         "coeffs_per_step": coeffs})
-    out.update({"roofline": rf, "rel_err": err, "dense": dense, "cpu_baseline": cpu})
+    out.update({"roofline": rf, "rel_err": err, "dense": dense, "adjoint": adj,
+                "cpu_baseline": cpu})
     return out
 
 
@@ -833,7 +889,12 @@ def main() -> int:
                     help="run the Fig. 4 speed comparison (markdown table) instead")
     ap.add_argument("--trace-summary", metavar="TRACE_DB",
                     help="summarise a rocprofv3 --kernel-trace database and exit (no GPU needed)")
+    ap.add_argument("--counter-summary", metavar="PMC_DB",
+                    help="summarise any rocprofv3 --pmc database and exit (no GPU needed)")
     args = ap.parse_args()
+    if args.counter_summary:
+        print(counter_summary(args.counter_summary))
+        return 0
     if args.trace_summary:
         print(trace_summary(args.trace_summary))
         return 0

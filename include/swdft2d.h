@@ -74,6 +74,10 @@
  *   SWDFT_TREE_WV         waves per strip of the forward tree (1 or 2)
  *   SWDFT_TREE_SLAB       window rows per workgroup of the forward tree
  *   SWDFT_ADJ_SLAB        dx rows per workgroup of swdft2d_backward
+ *   SWDFT_ADJ_KG          lanes per column stream of swdft2d_backward (1 or 2;
+ *                         2 is built for n0 >= 8 with n1 <= 32)
+ *   SWDFT_ADJ_WPC         resident workgroups per CU of swdft2d_backward
+ *                         (0 = no cap)
  *   SWDFT_DENSE_SLAB      window rows per workgroup of DENSE_BF16X2
  */
 #ifndef SWDFT2D_H

@@ -120,9 +120,16 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // dx rows per wave of the adjoint: a whole image column when that already
 // gives enough waves (no dy row is then read twice); otherwise slabs, each
 // primed by the n0-1 window rows below it.
-int32_t adj_slab(const swdft2d_plan_s* p) {
-  const int cr = swdft::tree_adj_rows_per_chunk(p->n0, p->n1);
-  const int64_t nstrips = ceil_div(p->P1, swdft::tree_adj_columns_per_wave(p->n0, p->n1));
+int32_t adj_kg(const swdft2d_plan_s* p) {
+  const int kg = env_int("SWDFT_ADJ_KG", 0);
+  return kg > 0 && swdft::tree_adj_kg_supported(p->n0, p->n1, kg)
+             ? kg
+             : swdft::tree_adj_default_kg(p->n0, p->n1);
+}
+
+int32_t adj_slab(const swdft2d_plan_s* p, int kg) {
+  const int cr = swdft::tree_adj_rows_per_chunk(p->n0, p->n1, kg);
+  const int64_t nstrips = ceil_div(p->P1, swdft::tree_adj_columns_per_wave(p->n0, p->n1, kg));
   const int64_t full = ceil_div(p->N0, cr) * cr;
   int64_t S = 0;
   const char* env = std::getenv("SWDFT_ADJ_SLAB");
@@ -149,8 +156,9 @@ swdft::AdjGeom adj_geom(const swdft2d_plan_s* p) {
   g.P0 = p->P0;
   g.P1 = p->P1;
   g.y_image_stride = p->P0 * p->P1 * p->n0 * p->n1;
-  g.S = adj_slab(p);
-  g.nstrips = (int32_t)ceil_div(p->P1, swdft::tree_adj_columns_per_wave(p->n0, p->n1));
+  g.kg = adj_kg(p);
+  g.S = adj_slab(p, g.kg);
+  g.nstrips = (int32_t)ceil_div(p->P1, swdft::tree_adj_columns_per_wave(p->n0, p->n1, g.kg));
   g.nslabs = (int32_t)ceil_div(p->N0, g.S);
   g.batch = (int32_t)p->batch;
   g.scale = p->norm == SWDFT_NORM_ORTHO ? (float)(1.0 / std::sqrt((double)p->n0 * p->n1)) : 1.0f;

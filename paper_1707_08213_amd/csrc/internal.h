@@ -87,6 +87,7 @@ struct AdjGeom {
   float scale;
   int32_t wpc;             // resident waves per CU: 0 = as many as fit, else capped
   int32_t lds_cu;          // LDS bytes per CU (used to impose the cap)
+  int32_t kg;              // lanes per column stream (k0 residues), 1 or 2
 };
 
 // Geometry of one dense (matrix-core) launch: one wave owns 16/n1 window
@@ -153,8 +154,10 @@ hipError_t launch_tree3_fwd(int n0, int n1, int n2, bool real_input, const void*
 
 hipError_t launch_tree_adj(int n0, int n1, bool real_input, const float2* dy, void* ws, void* dx,
                            const AdjGeom& g, const TwiddlesF32& tw, hipStream_t stream);
-int tree_adj_rows_per_chunk(int n0, int n1);
-int tree_adj_columns_per_wave(int n0, int n1);
+int tree_adj_rows_per_chunk(int n0, int n1, int kg);
+int tree_adj_columns_per_wave(int n0, int n1, int kg);
+int tree_adj_default_kg(int n0, int n1);
+bool tree_adj_kg_supported(int n0, int n1, int kg);
 // workspace elements (float for real input, float2 for complex) of one adjoint launch
 int64_t tree_adj_workspace_elems(int n0, int n1, const AdjGeom& g);
 

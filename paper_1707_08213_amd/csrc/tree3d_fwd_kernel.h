@@ -137,9 +137,9 @@ __device__ __forceinline__ void tree3_fwd_tile(const void* __restrict__ xv, floa
   const int cp_k2 = cp_k % N2W;
   // output of one window row: the strip's QW windows of n0*n1*n2 values
   float2* ystrip = yimg + ((int64_t)q1 * g.P2 + q2_0) * (N0W * C::NK);
-  const int64_t y_row_stride = g.P1 * g.P2 * (N0W * C::NK);
-  const uint32_t strip_bytes =
-      (uint32_t)(min((int64_t)C::QW, g.P2 - q2_0) * (N0W * C::NK * (int)sizeof(float2)));
+  const uint64_t row_bytes = (uint64_t)g.P1 * g.P2 * (N0W * C::NK * sizeof(float2));
+  const uint32_t strip_bytes = tree::uniform_u32(
+      (uint32_t)(min((int64_t)C::QW, g.P2 - q2_0) * (N0W * C::NK * (int)sizeof(float2))));
   const uint32_t lane_off = (uint32_t)((cp_c * (N0W * C::NK) + cp_k) * (int)sizeof(float2));
 
   float2 lanefac[CC::M0 + 1];
@@ -191,13 +191,15 @@ __device__ __forceinline__ void tree3_fwd_tile(const void* __restrict__ xv, floa
     load_chunk(crow + C::CR);
     __builtin_amdgcn_sched_barrier(0);
 
+    // step st writes window row q0 = crow + st - (n0 - 1) if it lies in the slab
+    const tree::StepSpan sp = tree::step_span(crow, row0, q0_end, N0W - 1, C::CR);
+    uint64_t row_addr = tree::uniform_u64((uint64_t)(uintptr_t)ystrip +
+                                          (uint64_t)(crow - (N0W - 1)) * row_bytes);
     sfor<0, C::CR>([&](auto STc) {
       constexpr int st = STc;
       const float2 z = zcol[st * C::ZROW];
-      const int64_t q0 = crow + st - (N0W - 1);
-      const bool row_store = (q0 >= row0) && (q0 < q0_end);
-      const auto out = buf_rsrc(ystrip + (row_store ? q0 : 0) * y_row_stride,
-                                row_store ? strip_bytes : 0u);
+      const auto out = tree::step_rsrc(row_addr, st, sp, strip_bytes);
+      row_addr += row_bytes;
       column_levels<N0W, 1, st % C::RING>(z, ring, lanefac, lw, tw.w0, [&](auto J, float2 v) {
         store_buf<C::NT_STORES>(out, lane_off + J * C::NK * (int)sizeof(float2), v);
       });

@@ -52,36 +52,6 @@ __device__ __forceinline__ float2 twmul_conj(float2 d, const float2* w) {
   }
 }
 
-// Transposed column levels u = m0..1 for one row p (descending order).
-// On entry g[k0] = G_{m0}[p][k0]; returns G_0[p] = dZ[p]. ring[u-1] holds
-// S_u of the next s_u rows below p (already processed); slot (p mod s_u)*h.
-// PM = p mod (n0/2), known at compile time.
-template <int N0W, int PM, int RING, int NLEV>
-__device__ __forceinline__ float2 column_levels_adj(const float2 (&g)[N0W],
-                                                    float2 (&ring)[NLEV][RING],
-                                                    const float2* w0) {
-  constexpr int M0 = ilog2(N0W);
-  float2 cur[N0W];
-  sfor<0, N0W>([&](auto K) { cur[K] = g[K]; });
-  sfor<0, M0>([&](auto V) {
-    constexpr int u = M0 - V;  // M0 .. 1
-    constexpr int s = N0W >> u;
-    constexpr int h = 1 << (u - 1);
-    constexpr int slot = (PM % s) * h;
-    float2 nxt[N0W];
-    sfor<0, h>([&](auto I) {
-      constexpr int i = I;
-      const float2 a = cur[i];
-      const float2 b = cur[i + h];
-      const float2 below = ring[u - 1][slot + i];
-      ring[u - 1][slot + i] = cadd(a, b);
-      nxt[i] = cadd(below, twmul_conj<i * s, N0W>(csub(a, b), w0));
-    });
-    sfor<0, h>([&](auto K) { cur[K] = nxt[K]; });
-  });
-  return cur[0];
-}
-
 // Transposed row levels t = m1..1 for one tree position p. On entry
 // v[k1] = dZ[k1]; on exit v[d] is the cotangent of x[p - d], d < n1.
 template <int N1W>
@@ -118,26 +88,102 @@ __device__ __forceinline__ float2 load_buf_nt(__amdgpu_buffer_rsrc_t r, uint32_t
 // whose register rings leave no room for more.
 constexpr int adj_prefetch_rows(int n0) { return n0 <= 16 ? 4 : 2; }
 
-template <int N0W, int N1W>
+// Lanes per column stream of the adjoint (k0 residues). Splitting a stream
+// over two lanes halves its rings and its dy registers, so n0 = 32 runs
+// without scratch; each load instruction then reads two adjacent k0 rows of
+// a window.
+constexpr bool adj_kg_built(int n0, int n1, int kg) {
+  return kg == 1 || (kg == 2 && n0 >= 8 && n1 <= 32);
+}
+
+template <int N0W, int N1W, int KG>
 struct AdjCfg {
   static constexpr int M0 = ilog2(N0W);
-  static constexpr int QW = 64 / N1W;
-  static constexpr int R = N1W;
+  static constexpr int G = ilog2(KG);
+  static constexpr int QW = 64 / (N1W * KG);                // window columns per strip
+  static constexpr int R = 64 / QW;                         // rows per row-adjoint pass
   static constexpr int RING = N0W > 1 ? N0W / 2 : 1;
   static constexpr int PF = adj_prefetch_rows(N0W);         // prefetch depth (rows)
   static constexpr int CR0 = R > RING ? R : RING;
   static constexpr int CR = CR0 > PF ? CR0 : PF;           // rows per chunk
   static constexpr int ZS = N1W + 1;
   static constexpr int ZROW = QW * ZS;
-  static constexpr int NLEV = M0 > 0 ? M0 : 1;
+  static constexpr int NL = N0W / KG;                       // dy values per lane and row
+  static_assert(KG == 1 || (KG == 2 && N0W >= 4), "streams split over at most two lanes");
+  static_assert(N1W * KG <= 64, "one wave holds a whole window column");
+  static_assert(CR % PF == 0, "prefetch slots are static");
   static constexpr int WCOLS = QW + N1W - 1;                // x columns a strip touches
 };
 
-template <int N0W, int N1W, bool REAL>
+// Transposed column levels u = m0..1 for one row p (descending order) of a
+// stream whose k0 values are split over KG lanes (residue r = lane part):
+// on entry g[j] = G_{m0}[p][r + KG j]; the result is G_0[p] = dZ[p] (the same
+// in the KG lanes of the stream). ring holds, per level u, the pair sums
+// S_u[p'][i] = G_u[p'][i] + G_u[p'][i + h] of the next s_u rows below p
+// (already processed) for the nodes i this lane keeps: the layout of ColCfg
+// (slot (p mod s_u) * held(u - 1)). For a level whose pairs lie in one lane
+// (h = 2^{u-1} >= KG) the pair (i, i + h) has one residue; the level with
+// h < KG (u = 1 for KG = 2) combines the two lanes of a stream, whose values
+// are exchanged with the partner lane (other(v)). PM = p mod (n0/2), known at
+// compile time. conj(Omega0[i s]) = conj(Omega0[r s]) conj(Omega0[KG j s]):
+// the lane part comes from lanefac (conj of the forward factor), the uniform
+// part from the table; where the uniform part is not 1 or -i, the product
+// lwc[u][j] = conj(Omega0[(r + KG j) s]) is precomputed per lane.
+template <int N0W, int KG, int PM, typename Other>
+__device__ __forceinline__ float2 column_levels_adj(
+    const float2 (&g)[N0W / KG], float2 (&ring)[ColCfg<N0W, KG>::RING_TOTAL],
+    const float2 (&lanefac)[ColCfg<N0W, KG>::M0 + 1],
+    const float2 (&lwc)[ColCfg<N0W, KG>::M0 + 1][ColCfg<N0W, KG>::LW], const float2* w0,
+    bool upper, Other&& other) {
+  using CC = ColCfg<N0W, KG>;
+  float2 cur[N0W / KG];
+  sfor<0, N0W / KG>([&](auto K) { cur[K] = g[K]; });
+  sfor<0, CC::M0>([&](auto V) {
+    constexpr int u = CC::M0 - V;  // M0 .. 1
+    constexpr int s = N0W >> u;
+    constexpr int hp = CC::held(u - 1);
+    constexpr int base = CC::ring_off(u) + (PM % s) * hp;
+    if constexpr (u - 1 >= CC::G) {
+      // pairs (r + KG j, r + KG j + h) inside the lane: j < hp, partner j + hp
+      float2 nxt[N0W / KG];
+      sfor<0, hp>([&](auto J) {
+        constexpr int j = J;
+        const float2 a = cur[j];
+        const float2 b = cur[j + hp];
+        const float2 below = ring[base + j];
+        ring[base + j] = cadd(a, b);
+        float2 d = csub(a, b);
+        if constexpr (CC::folded(u, j)) {
+          d = cmul(lwc[u][j], d);
+        } else {
+          if constexpr (KG > 1) d = cmul(lanefac[u], d);
+          d = twmul_conj<KG * j * s, N0W>(d, w0);
+        }
+        nxt[j] = cadd(below, d);
+      });
+      sfor<0, hp>([&](auto K) { cur[K] = nxt[K]; });
+    } else {
+      // u = 1 with two lanes per stream: the lane of residue 0 holds node 0,
+      // its partner node 1; both form node 0 of level 0 (twiddle 1)
+      static_assert(u == 1 && KG == 2, "cross-lane level only for KG = 2");
+      const float2 mine = cur[0];
+      const float2 theirs = other(mine);
+      const float2 lo = upper ? theirs : mine;
+      const float2 hi = upper ? mine : theirs;
+      const float2 below = ring[base];
+      ring[base] = cadd(lo, hi);
+      cur[0] = cadd(below, csub(lo, hi));
+    }
+  });
+  return cur[0];
+}
+
+template <int N0W, int N1W, bool REAL, int KG>
 __global__ __launch_bounds__(64) void tree_adj_kernel(const float2* __restrict__ dy,
                                                       void* __restrict__ wsv, AdjGeom g,
                                                       TwiddlesF32 tw) {
-  using C = AdjCfg<N0W, N1W>;
+  using C = AdjCfg<N0W, N1W, KG>;
+  using CC = ColCfg<N0W, KG>;
   __shared__ float2 zl[C::CR * C::ZROW];
 
   const int lane = threadIdx.x;
@@ -160,39 +206,78 @@ __global__ __launch_bounds__(64) void tree_adj_kernel(const float2* __restrict__
 
   const float2* dyimg = dy + b * g.y_image_stride;
 
-  // column-phase roles
-  const int cp_c = lane / N1W;
+  // column-phase roles: lane (c, residue, k1)
+  const int cp_c = lane / (N1W * KG);
+  const int cp_res = (lane / N1W) % KG;
   const int cp_k1 = lane % N1W;
   // dy of one window row of the strip: QW windows from dystrip + q0 *
-  // y_row_stride, of which the first strip_bytes exist; lanes past the right
-  // edge read zero through the buffer resource's range check
+  // row_bytes, of which the first strip_bytes exist; lanes past the right
+  // edge read zero through the buffer resource's range check. A load
+  // instruction reads KG adjacent k0 rows of n1 values of each window.
   const float2* dystrip = dyimg + q1_0 * (N0W * N1W);
-  const int64_t y_row_stride = g.P1 * (N0W * N1W);
-  const uint32_t strip_bytes =
-      (uint32_t)(min((int64_t)C::QW, g.P1 - q1_0) * (N0W * N1W * (int)sizeof(float2)));
-  const uint32_t lane_off = (uint32_t)((cp_c * (N0W * N1W) + cp_k1) * (int)sizeof(float2));
+  const uint64_t row_bytes = (uint64_t)g.P1 * (N0W * N1W * sizeof(float2));
+  const uint32_t strip_bytes = uniform_u32(
+      (uint32_t)(min((int64_t)C::QW, g.P1 - q1_0) * (N0W * N1W * (int)sizeof(float2))));
+  const uint32_t lane_off =
+      (uint32_t)((cp_c * (N0W * N1W) + cp_res * N1W + cp_k1) * (int)sizeof(float2));
   // row-phase roles
   const int rp_r = lane / C::QW;
   const int rp_c = lane % C::QW;
 
-  float2 ring[C::NLEV][C::RING];
-  sfor<0, C::NLEV>([&](auto L) {
-    sfor<0, C::RING>([&](auto K) { ring[L][K] = make_float2(0.f, 0.f); });
-  });
-
-  // rows without a window of this slab get an empty resource (all zeros)
-  auto load_step = [&](int64_t gstep, float2 (&dst)[N0W]) {
-    const int64_t p = p_top - gstep;
-    const int64_t q0 = p - (N0W - 1);
-    const bool ok = q0 >= 0 && q0 <= q0_last && p >= r0;
-    const auto rs = buf_rsrc(dystrip + (ok ? q0 : 0) * y_row_stride, ok ? strip_bytes : 0u);
-    sfor<0, N0W>([&](auto K) {
-      dst[K] = load_buf_nt(rs, lane_off + K * N1W * (int)sizeof(float2));
+  // per-lane twiddle parts of a split stream (see column_levels_adj)
+  const float2* const w0 = tw.w0;
+  float2 lanefac[CC::M0 + 1];
+  float2 lwc[CC::M0 + 1][CC::LW];
+  sfor<0, CC::M0 + 1>([&](auto U) {
+    constexpr int u = U;
+    if constexpr (KG > 1 && u > 0) {
+      const float2 f = w0[(cp_res & ((1 << u) - 1)) * (N0W >> u)];
+      lanefac[u] = make_float2(f.x, -f.y);
+    } else {
+      lanefac[u] = make_float2(1.f, 0.f);
+    }
+    sfor<0, CC::LW>([&](auto J) {
+      constexpr int j = J;
+      if constexpr (u > 0 && CC::folded(u, j)) {
+        const float2 f = w0[((cp_res + KG * j) * (N0W >> u)) % N0W];
+        lwc[u][j] = make_float2(f.x, -f.y);
+      }
     });
+  });
+  // the partner lane of a split stream (residue r ^ 1) and which of the two
+  // holds node 1 at the cross-lane level
+  const bool upper = (cp_res & 1) != 0;
+  auto other = [&](float2 v) {
+    return make_float2(__shfl_xor(v.x, N1W), __shfl_xor(v.y, N1W));
   };
 
-  float2 pf[C::PF][N0W];
-  sfor<0, C::PF>([&](auto S) { load_step(S, pf[S]); });
+  float2 ring[CC::RING_TOTAL];
+  sfor<0, CC::RING_TOTAL>([&](auto K) { ring[K] = make_float2(0.f, 0.f); });
+
+  // dy rows are loaded in step order gstep = 0, 1, ...: position p = p_top -
+  // gstep, window row q0 = p - (n0 - 1). Only q0 in [0, q0_last] with p >= r0
+  // exist for this slab (a contiguous range of steps); the others read zeros
+  // (an empty resource), which also gives the incomplete trees of Sec. 4.7
+  // zero gradient. The row address is a running scalar value.
+  const int64_t g_first = p_top - (N0W - 1) - q0_last;
+  const int64_t g_last = min(p_top - (N0W - 1), p_top - r0);
+  const StepSpan lsp{(int)uniform_u32((uint32_t)max<int64_t>(0, g_first)),
+                     (uint32_t)uniform_u32((uint32_t)max<int64_t>(
+                         0, g_last - max<int64_t>(0, g_first) + 1))};
+  uint64_t dy_addr = uniform_u64((uint64_t)(uintptr_t)dystrip +
+                                 (uint64_t)(p_top - (N0W - 1)) * row_bytes);
+  int gstep = 0;
+  auto load_step = [&](float2 (&dst)[C::NL]) {
+    const auto rs = step_rsrc(dy_addr, gstep, lsp, strip_bytes);
+    sfor<0, C::NL>([&](auto K) {
+      dst[K] = load_buf_nt(rs, lane_off + K * KG * N1W * (int)sizeof(float2));
+    });
+    dy_addr -= row_bytes;
+    ++gstep;
+  };
+
+  float2 pf[C::PF][C::NL];
+  sfor<0, C::PF>([&](auto S) { load_step(pf[S]); });
 
   float* wsr = reinterpret_cast<float*>(wsv);
   float2* wsc = reinterpret_cast<float2*>(wsv);
@@ -207,22 +292,22 @@ __global__ __launch_bounds__(64) void tree_adj_kernel(const float2* __restrict__
       // p mod (n0/2): p_top + 1 is a multiple of CR, hence of n0/2
       constexpr int pm = (C::RING - 1 - (st % C::RING));
       float2 dz;
-      if constexpr (N0W >= 32) {
+      if constexpr (N0W == 1) {
+        dz = pf[slot][0];
+        load_step(pf[slot]);
+      } else if constexpr (N0W / KG >= 32) {
         // the rings fill the registers: use the prefetched row in place and
         // refill its slot afterwards (no second copy of 32 values)
-        dz = column_levels_adj<N0W, pm>(pf[slot], ring, tw.w0);
-        load_step(cbase + st + C::PF, pf[slot]);
+        dz = column_levels_adj<N0W, KG, pm>(pf[slot], ring, lanefac, lwc, tw.w0, upper, other);
+        load_step(pf[slot]);
       } else {
-        float2 gcur[N0W];
-        sfor<0, N0W>([&](auto K) { gcur[K] = pf[slot][K]; });
-        load_step(cbase + st + C::PF, pf[slot]);
-        if constexpr (N0W == 1) {
-          dz = gcur[0];
-        } else {
-          dz = column_levels_adj<N0W, pm>(gcur, ring, tw.w0);
-        }
+        float2 gcur[C::NL];
+        sfor<0, C::NL>([&](auto K) { gcur[K] = pf[slot][K]; });
+        load_step(pf[slot]);
+        dz = column_levels_adj<N0W, KG, pm>(gcur, ring, lanefac, lwc, tw.w0, upper, other);
       }
-      zl[st * C::ZROW + cp_c * C::ZS + cp_k1] = dz;
+      // the KG lanes of a stream hold the same dZ; the residue-0 lane writes it
+      if (KG == 1 || cp_res == 0) zl[st * C::ZROW + cp_c * C::ZS + cp_k1] = dz;
     });
     __syncthreads();
 
@@ -268,10 +353,9 @@ __global__ __launch_bounds__(64) void tree_adj_kernel(const float2* __restrict__
 
 // dx[b][r][c] = sum over strips s whose columns [s*QW, s*QW + QW + n1 - 1)
 // contain c of ws[b][s][r][c - s*QW], in ascending s.
-template <int N1W, bool REAL>
+template <int QW, int N1W, bool REAL>
 __global__ __launch_bounds__(256) void tree_adj_reduce_kernel(const void* __restrict__ wsv,
                                                               void* __restrict__ dxv, AdjGeom g) {
-  constexpr int QW = 64 / N1W;
   constexpr int WCOLS = QW + N1W - 1;
   const int64_t total = (int64_t)g.batch * g.N0 * g.N1;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -299,21 +383,31 @@ __global__ __launch_bounds__(256) void tree_adj_reduce_kernel(const void* __rest
   }
 }
 
-template <int N0W, int N1W, bool REAL>
-hipError_t launch_adj_one(const float2* dy, void* ws, void* dx, const AdjGeom& g,
-                          const TwiddlesF32& tw, hipStream_t stream) {
+template <int N0W, int N1W, bool REAL, int KG>
+hipError_t launch_adj_kg(const float2* dy, void* ws, void* dx, const AdjGeom& g,
+                         const TwiddlesF32& tw, hipStream_t stream) {
   const int64_t nb = (int64_t)g.batch * g.nslabs * g.nstrips;
-  using C = AdjCfg<N0W, N1W>;
+  using C = AdjCfg<N0W, N1W, KG>;
   const unsigned pad =
       occupancy_lds(g.wpc, g.lds_cu, C::CR * C::ZROW * (unsigned)sizeof(float2));
-  hipLaunchKernelGGL((tree_adj_kernel<N0W, N1W, REAL>), dim3((unsigned)nb), dim3(64), pad, stream,
-                     dy, ws, g, tw);
+  hipLaunchKernelGGL((tree_adj_kernel<N0W, N1W, REAL, KG>), dim3((unsigned)nb), dim3(64), pad,
+                     stream, dy, ws, g, tw);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t total = (int64_t)g.batch * g.N0 * g.N1;
-  hipLaunchKernelGGL((tree_adj_reduce_kernel<N1W, REAL>), dim3((unsigned)((total + 255) / 256)),
-                     dim3(256), 0, stream, ws, dx, g);
+  hipLaunchKernelGGL((tree_adj_reduce_kernel<C::QW, N1W, REAL>),
+                     dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, ws, dx, g);
   return hipGetLastError();
+}
+
+template <int N0W, int N1W, bool REAL>
+hipError_t launch_adj_one(const float2* dy, void* ws, void* dx, const AdjGeom& g,
+                          const TwiddlesF32& tw, hipStream_t stream) {
+  if constexpr (adj_kg_built(N0W, N1W, 2)) {
+    if (g.kg == 2) return launch_adj_kg<N0W, N1W, REAL, 2>(dy, ws, dx, g, tw, stream);
+  }
+  if (g.kg == 1) return launch_adj_kg<N0W, N1W, REAL, 1>(dy, ws, dx, g, tw, stream);
+  return hipErrorInvalidValue;
 }
 
 template <int N0W, bool REAL>

@@ -294,6 +294,36 @@ __device__ __forceinline__ void store_buf_nt(__amdgpu_buffer_rsrc_t r, uint32_t 
   store_buf<true>(r, off, v);
 }
 
+// Rows of one chunk of steps that touch a row buffer: step st of a chunk that
+// starts at input row crow is window row q = crow + st - lag, and only rows
+// in [q_begin, q_end) are real (the others prime the rings or lie past the
+// slab). [lo, lo + span) are those steps, as scalar values.
+struct StepSpan {
+  int lo;
+  uint32_t span;
+};
+
+__device__ __forceinline__ StepSpan step_span(int64_t crow, int64_t q_begin, int64_t q_end, int lag,
+                                              int steps) {
+  const int lo =
+      (int)uniform_u32((uint32_t)max<int64_t>(0, min<int64_t>(q_begin + lag - crow, steps)));
+  const int hi =
+      (int)uniform_u32((uint32_t)max<int64_t>(lo, min<int64_t>(q_end + lag - crow, steps)));
+  return StepSpan{lo, (uint32_t)(hi - lo)};
+}
+
+// Buffer resource of one row for step st: the row's address (an integer
+// kept in scalar registers and advanced by one row per step by the caller,
+// so a step spends a few scalar instructions on its resource; the tile's rate
+// is bounded by a wave's instruction issue) and nbytes, or an empty range on
+// the steps outside the span. The address of a step outside the span may lie
+// outside the buffer; it is never dereferenced.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t step_rsrc(uint64_t addr, int st, StepSpan sp,
+                                                            uint32_t nbytes) {
+  return buf_rsrc((const void*)(uintptr_t)uniform_u64(addr),
+                  uniform_u32((uint32_t)(st - sp.lo) < sp.span ? nbytes : 0u));
+}
+
 // Workgroup i runs on XCD i mod 8; give each XCD a contiguous block of tiles.
 __device__ __forceinline__ int xcd_tile(int id, int nb) {
   constexpr int kXcd = 8;
@@ -483,18 +513,10 @@ __device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float
     float2 zq[C::CR];
     sfor<0, (kLdsAhead < C::CR ? kLdsAhead : C::CR)>([&](auto K) { zq[K] = zcol[K * C::ZROW]; });
     // Step st writes window row q0 = crow + st - (n0 - 1) when row0 <= q0 <
-    // q0_end, i.e. for st in [st_lo, st_hi); the other steps prime the rings
-    // (or run past the slab) and get an empty resource. The row's address is
-    // kept as a running scalar value, so a step spends a handful of scalar
-    // instructions on its resource (a wave's instruction issue bounds the
-    // tile: a 64-bit multiply and compare per row cost about 8% of the rate).
-    const int st_lo = (int)uniform_u32(
-        (uint32_t)max<int64_t>(0, min<int64_t>(row0 + (N0W - 1) - crow, C::CR)));
-    const int st_hi = (int)uniform_u32(
-        (uint32_t)max<int64_t>(st_lo, min<int64_t>(q0_end + (N0W - 1) - crow, C::CR)));
-    const uint32_t st_span = (uint32_t)(st_hi - st_lo);
-    // address of row crow - (n0 - 1), as an integer: the first rows of the
-    // top slab lie before y and are never written
+    // q0_end; the other steps prime the rings (or run past the slab) and get
+    // an empty resource. row_addr is the address of row q0 of step 0 (as an
+    // integer: the priming rows of the top slab lie before y).
+    const StepSpan sp = step_span(crow, row0, q0_end, N0W - 1, C::CR);
     uint64_t row_addr = uniform_u64((uint64_t)(uintptr_t)ystrip +
                                     (uint64_t)(crow - (N0W - 1)) * row_bytes);
     sfor<0, C::CR>([&](auto STc) {
@@ -502,8 +524,7 @@ __device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float
       if constexpr (st + kLdsAhead < C::CR) zq[st + kLdsAhead] = zcol[(st + kLdsAhead) * C::ZROW];
       __builtin_amdgcn_sched_barrier(0);  // keep the read ahead of this step's work
       const float2 z = zq[st];
-      const uint32_t nbytes = uniform_u32((uint32_t)(st - st_lo) < st_span ? strip_bytes : 0u);
-      const auto out = buf_rsrc((const void*)(uintptr_t)uniform_u64(row_addr), nbytes);
+      const auto out = step_rsrc(row_addr, st, sp, strip_bytes);
       row_addr += row_bytes;
       if constexpr (N0W == 1) {
         store_buf<C::NT_STORES>(out, lane_off, z);

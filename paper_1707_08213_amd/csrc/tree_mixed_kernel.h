@@ -283,9 +283,9 @@ __global__ __launch_bounds__(64) void tree_mixed_kernel(const void* __restrict__
   const int cp_c = cp_live ? cp_c_raw : C::QW - 1;
   const int cp_k1 = lane % N1W;
   float2* ystrip = yimg + q1_0 * (N0W * N1W);
-  const int64_t y_row_stride = g.P1 * (N0W * N1W);
-  const uint32_t strip_bytes =
-      (uint32_t)(min((int64_t)C::QW, g.P1 - q1_0) * (N0W * N1W * (int)sizeof(float2)));
+  const uint64_t row_bytes = (uint64_t)g.P1 * (N0W * N1W * sizeof(float2));
+  const uint32_t strip_bytes = tree::uniform_u32(
+      (uint32_t)(min((int64_t)C::QW, g.P1 - q1_0) * (N0W * N1W * (int)sizeof(float2))));
   const uint32_t lane_off =
       cp_live ? (uint32_t)((cp_c * (N0W * N1W) + cp_k1) * (int)sizeof(float2)) : kOutOfRange;
 
@@ -323,16 +323,18 @@ __global__ __launch_bounds__(64) void tree_mixed_kernel(const void* __restrict__
     __builtin_amdgcn_sched_barrier(0);
     // one ring period unrolled (its slots are fixed registers), repeated
     const float2* zcol = zl + cp_c * C::ZS + cp_k1;
+    // step `row` writes window row q0 = crow + row - (n0 - 1) if it lies in the slab
+    const tree::StepSpan sp = tree::step_span(crow, row0, q0_end, N0W - 1, C::CR);
+    uint64_t row_addr = tree::uniform_u64((uint64_t)(uintptr_t)ystrip +
+                                          (uint64_t)(crow - (N0W - 1)) * row_bytes);
 #pragma clang loop unroll(disable)
     for (int sc = 0; sc < C::CR / C::PERIOD; ++sc) {
       sfor<0, C::PERIOD>([&](auto STc) {
         constexpr int st = STc;
         const int row = sc * C::PERIOD + st;
         const float2 z = zcol[row * C::ZROW];
-        const int64_t q0 = crow + row - (N0W - 1);
-        const bool row_store = (q0 >= row0) && (q0 < q0_end);
-        const auto out = buf_rsrc(ystrip + (row_store ? q0 : 0) * y_row_stride,
-                                  row_store ? strip_bytes : 0u);
+        const auto out = tree::step_rsrc(row_addr, row, sp, strip_bytes);
+        row_addr += row_bytes;
         if constexpr (N0W == 1) {
           store_buf<C::NT_STORES>(out, lane_off, z);
         } else {

@@ -64,9 +64,9 @@ __global__ __launch_bounds__(64) void tree_stream_kernel(const void* __restrict_
   const int cp_res = (lane / N1W) % KG;
   const int cp_k1 = lane % N1W;
   float2* ystrip = y + q1_0 * (N0W * N1W);
-  const int64_t y_row_stride = sg.P1 * (N0W * N1W);
-  const uint32_t strip_bytes =
-      (uint32_t)(min((int64_t)C::QW, sg.P1 - q1_0) * (N0W * N1W * (int)sizeof(float2)));
+  const uint64_t row_bytes = (uint64_t)sg.P1 * (N0W * N1W * sizeof(float2));
+  const uint32_t strip_bytes = uniform_u32(
+      (uint32_t)(min((int64_t)C::QW, sg.P1 - q1_0) * (N0W * N1W * (int)sizeof(float2))));
   const uint32_t lane_off =
       (uint32_t)((cp_c * (N0W * N1W) + cp_res * N1W + cp_k1) * (int)sizeof(float2));
 
@@ -166,15 +166,20 @@ __global__ __launch_bounds__(64) void tree_stream_kernel(const void* __restrict_
     load_chunk(rel0 + C::CR);  // past the call's rows: zeros, no memory touched
     __builtin_amdgcn_sched_barrier(0);
 
-    // ---- column phase: the chunk's rows that this call carries
+    // ---- column phase: the chunk's rows that this call carries. Step st
+    // completes window row q0 = p_start + rel0 + st - (n0 - 1) when q0 >= 0;
+    // row_addr is the address of that row of step 0 (an integer: it may lie
+    // before y).
+    const int64_t crow = p_start + rel0;
+    const StepSpan sp = step_span(crow, 0, crow + C::CR, N0W - 1, C::CR);
+    uint64_t row_addr = uniform_u64((uint64_t)(uintptr_t)ystrip +
+                                    (uint64_t)(crow - (N0W - 1) - q0_first) * row_bytes);
     sfor<0, C::CR>([&](auto STc) {
       constexpr int st = STc;
+      const auto out = step_rsrc(row_addr, st, sp, strip_bytes);
+      row_addr += row_bytes;
       if (rel0 + st < R) {
         const float2 z = zl[st * C::ZROW + cp_c * C::ZS + cp_k1];
-        const int64_t q0 = p_start + rel0 + st - (N0W - 1);
-        const bool row_store = q0 >= 0;
-        const auto out = buf_rsrc(ystrip + (row_store ? q0 - q0_first : 0) * y_row_stride,
-                                  row_store ? strip_bytes : 0u);
         // Non-temporal stores for every n1. Plain stores for the narrow rows
         // of n1 < 16, which help the long single-plan launches, measured
         // slower for these short calls (1024-wide rows in 64-row pushes,

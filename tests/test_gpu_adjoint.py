@@ -75,6 +75,31 @@ def test_adjoint_slab_boundaries(swd, orc, n0, n1, slab):
         assert rel_err(got[b], ref) <= TOL
 
 
+@pytest.mark.parametrize("kg", [1, 2])
+@pytest.mark.parametrize("n0,n1,slab", [(8, 1, 0), (8, 8, 16), (16, 4, 0), (16, 16, 32),
+                                        (16, 32, 0), (32, 1, 0), (32, 8, 16), (32, 16, 32),
+                                        (32, 32, 0)])
+def test_adjoint_lane_split(swd, orc, monkeypatch, n0, n1, slab, kg):
+    """A column stream of the adjoint split over one or two lanes by k0
+    residue (two lanes exchange their level-1 nodes), real and complex, with
+    one slab or several (slab > 0): both against the oracle's explicit
+    adjoint (the transpose of Eq. (5)-(6))."""
+    monkeypatch.setenv("SWDFT_ADJ_KG", str(kg))
+    if slab:
+        monkeypatch.setenv("SWDFT_ADJ_SLAB", str(slab))
+    N0 = (3 * slab if slab else 2 * n0) + n0 + 5
+    N1 = 3 * (64 // (n1 * kg)) + n1 + 5
+    P0, P1 = N0 - n0 + 1, N1 - n1 + 1
+    rng = np.random.default_rng(31 + 64 * n0 + n1 + kg)
+    dy = (rng.standard_normal((P0, P1, n0, n1)) +
+          1j * rng.standard_normal((P0, P1, n0, n1))).astype(np.complex64)
+    got = gpu_backward(swd, dy, N0, N1, torch.float32)
+    ref = orc.swdft2d_adjoint(dy.astype(np.complex128), N0, N1)
+    assert rel_err(got, ref.real) <= TOL
+    gotc = gpu_backward(swd, dy, N0, N1, torch.complex64)
+    assert rel_err(gotc, ref) <= TOL
+
+
 @pytest.mark.parametrize("n0,n1,slab", [(16, 16, 16), (32, 8, 32), (4, 2, 4), (8, 32, 32)])
 def test_forward_slab_boundaries(swd, orc, n0, n1, slab):
     """Forward with many slabs: the n0-1 priming rows at each slab top."""

@@ -1,0 +1,81 @@
+"""The allocation-free adjoint entry point, swdft2d_backward_noalloc, through
+the C ABI: on two calls in a row (the second with a smaller input) its dx
+must equal swdft2d_backward's bit for bit (same kernels, same launch shape;
+only the workspace differs: the library's per-device scratch array instead
+of a plan-owned allocation), and a plan whose workspace exceeds the scratch
+limit is rejected with SWDFT_E_NOMEM before anything is enqueued."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def swd():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_1707_08213_amd as swd
+    return swd
+
+
+def _plan(lib, N0, N1, n0, n1, dtype, batch):
+    h = ctypes.c_void_p()
+    assert lib.swdft2d_plan(ctypes.byref(h), N0, N1, n0, n1, dtype, batch) == 0
+    return h
+
+
+def _dy(shape, seed, dtype=np.complex64):
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(dtype)
+
+
+@pytest.mark.parametrize("real", [True, False])
+def test_noalloc_matches_backward_twice(swd, real):
+    from paper_1707_08213_amd import _lib
+    lib = _lib.lib
+    dt = _lib.SWDFT_R32 if real else _lib.SWDFT_C32
+    xdt = torch.float32 if real else torch.complex64
+    stream = torch.cuda.current_stream().cuda_stream
+    # first a larger input, then a smaller one: the scratch array keeps the
+    # first call's contents, which must not leak into the second result
+    for (B, N0, N1, n0, n1, seed) in [(3, 300, 260, 16, 16, 1), (1, 70, 90, 32, 8, 2)]:
+        P0, P1 = N0 - n0 + 1, N1 - n1 + 1
+        dy = torch.from_numpy(_dy((B, P0, P1, n0, n1), seed)).cuda()
+        ref = torch.empty((B, N0, N1), dtype=xdt, device="cuda")
+        got = torch.full((B, N0, N1), float("nan"), dtype=xdt, device="cuda")
+        h = _plan(lib, N0, N1, n0, n1, dt, B)
+        try:
+            print(f"[case] backward_noalloc B={B} N={N0}x{N1} n={n0}x{n1} real={real}", flush=True)
+            assert lib.swdft2d_backward(h, dy.data_ptr(), ref.data_ptr(), stream) == 0
+            assert lib.swdft2d_backward_noalloc(h, dy.data_ptr(), got.data_ptr(), stream) == 0, \
+                lib.swdft2d_last_error()
+            torch.cuda.synchronize()
+        finally:
+            lib.swdft2d_destroy(h)
+        assert torch.equal(torch.view_as_real(got) if not real else got,
+                           torch.view_as_real(ref) if not real else ref)
+
+
+def test_noalloc_rejects_beyond_limit(swd):
+    from paper_1707_08213_amd import _lib
+    lib = _lib.lib
+    # a 4096 x 4096 complex image with 32 x 8 windows needs about 370 MB of
+    # workspace, far beyond SWDFT_NOALLOC_SCRATCH_BYTES (32 MiB): rejected
+    # before any launch, nothing written
+    N0 = N1 = 4096
+    h = _plan(lib, N0, N1, 32, 8, _lib.SWDFT_C32, 1)
+    try:
+        need = (N0 - 31) * (N1 - 7) * 32 * 8
+        dy = torch.zeros(need, dtype=torch.complex64, device="cuda")
+        dx = torch.full((N0 * N1,), 7.0, dtype=torch.complex64, device="cuda")
+        st = lib.swdft2d_backward_noalloc(h, dy.data_ptr(), dx.data_ptr(),
+                                          torch.cuda.current_stream().cuda_stream)
+        assert _lib.STATUS[st] == "SWDFT_E_NOMEM", _lib.STATUS.get(st)
+        assert b"scratch" in lib.swdft2d_last_error()
+        torch.cuda.synchronize()
+        assert bool((dx == 7.0).all())
+    finally:
+        lib.swdft2d_destroy(h)
