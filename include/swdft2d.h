@@ -235,6 +235,27 @@ swdft_status_t swdft2d_plan_batched(swdft2d_plan_t* out, const swdft2d_desc_t* d
  * exec. R64/C64 plans have nothing to tune (returns SWDFT_OK). */
 swdft_status_t swdft2d_tune(swdft2d_plan_t plan, const void* x, void* y, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (work recorded under
+ * stream capture, serving loops that forbid allocation): swdft2d_backward
+ * with its workspace in a fixed array of the library, one per device
+ * (SWDFT_NOALLOC_SCRATCH_BYTES bytes, held from the first call on a device
+ * until the process ends), instead of a plan-owned allocation. Arguments,
+ * layouts, checks and result are those of swdft2d_backward (the same
+ * kernels and launch shape: dx is bitwise equal). It calls no allocation
+ * routine; the first call on a device looks up the array's device address.
+ * Checks: those of swdft2d_backward, then E_NOMEM when the adjoint's
+ * workspace exceeds SWDFT_NOALLOC_SCRATCH_BYTES: batch * ceil(P1 / W) * N0 *
+ * (W + n1 - 1) elements of 4 bytes (R32) or 8 bytes (C32), W = 64 / (n1 kg)
+ * window columns per strip, kg = 2 for n0 = 32 and 1 otherwise (about 19 MB
+ * for 1024 x 1024 with 16 x 16 windows). Nothing is enqueued on an error.
+ * All calls on one device share that device's array: calls that overlap in
+ * time on one device (other streams, other threads, other plans) race and
+ * give wrong results; order them. The array keeps the last call's contents
+ * (every call overwrites all of it that it reads). */
+#define SWDFT_NOALLOC_SCRATCH_BYTES (32u * 1024u * 1024u)
+swdft_status_t swdft2d_backward_noalloc(swdft2d_plan_t plan, const void* dy, void* dx,
+                                        hipStream_t stream);
+
 /* Copy the plan's FP32 twiddle vector of one axis (Sec. 4.2: Omega^0 for
  * axis 0, length n0; Omega^1 for axis 1, length n1) into out as interleaved
  * (re, im) floats, out[2m] + i out[2m+1] = Omega[m] = exp(-2 pi i m / n)

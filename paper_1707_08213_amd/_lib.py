@@ -39,6 +39,7 @@ SIGNATURES = {
     "swdft2d_set_algo": (_int, [_vp, _int]),
     "swdft2d_exec": (_int, [_vp, _vp, _vp, _vp]),
     "swdft2d_backward": (_int, [_vp, _vp, _vp, _vp]),
+    "swdft2d_backward_noalloc": (_int, [_vp, _vp, _vp, _vp]),
     "swdft2d_destroy": (_int, [_vp]),
     "swdft2d_output_elems": (_i64, [_vp]),
     "swdft2d_output_bytes": (_i64, [_vp]),

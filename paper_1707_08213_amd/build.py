@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIBRARY = os.path.join(PKG, "libswdft2d.so")
-SOURCES = ["abi.hip", "abi3d.hip", "abi_stream.hip", "tree3d_fwd.hip", "tree_stream.hip",
+SOURCES = ["abi.hip", "abi_noalloc.hip", "abi3d.hip", "abi_stream.hip", "tree3d_fwd.hip", "tree_stream.hip",
            "batched_host.hip", "tune.hip",
            "tree_config.hip", "tree_fwd.hip",
            "write_probe.hip", "tree_adj.hip", "direct_f64.hip", "swfft_r.hip", "swfft_c.hip",

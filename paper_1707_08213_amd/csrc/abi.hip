@@ -286,6 +286,41 @@ swdft_status_t check_buffers(const swdft2d_plan_s* p, const void* in, int64_t in
   return SWDFT_OK;
 }
 
+swdft_status_t backward_prepare(swdft2d_plan_t plan, const void* dy, void* dx, AdjGeom* g,
+                                size_t* ws_bytes) {
+  if (!is_live(plan)) return fail(SWDFT_E_PLAN, "null or destroyed plan");
+  if (plan->kind == 1) return fail(SWDFT_E_PLAN, "backward is not available for batched plans");
+  if (plan->n0 > SWDFT_MAX_WINDOW_ADJ || plan->n1 > SWDFT_MAX_WINDOW_ADJ || mixed_window(plan))
+    return fail(SWDFT_E_WINDOW, "backward supports power-of-two windows up to %d, not %d x %d",
+                SWDFT_MAX_WINDOW_ADJ, plan->n0, plan->n1);
+  const swdft2d_plan_s* p = plan;
+  const int64_t xb = p->batch * p->N0 * p->N1 * x_elem_bytes(p->dtype);
+  const int64_t yb = swdft2d_output_bytes(plan);
+  swdft_status_t st = check_buffers(p, dy, y_elem_bytes(p->dtype), yb, dx,
+                                    x_elem_bytes(p->dtype), xb, "dy", "dx");
+  if (st != SWDFT_OK) return st;
+  // The adjoint is always the transposed tree, whichever forward kernel an
+  // AUTO plan ends up running (the tuner may pick the dense variant for the
+  // forward transform; the adjoint of the map x -> y is the same).
+  if (f64_dtype(p->dtype) || (p->algo != SWDFT_ALGO_AUTO && p->algo != SWDFT_ALGO_TREE))
+    return fail(SWDFT_E_DTYPE, "backward runs the transposed tree; it needs an R32/C32 plan "
+                "with the TREE (or AUTO) algorithm");
+  *g = adj_geom(p);
+  *ws_bytes =
+      (size_t)swdft::tree_adj_workspace_elems(p->n0, p->n1, *g) * (real_dtype(p->dtype) ? 4 : 8);
+  return SWDFT_OK;
+}
+
+swdft_status_t backward_launch(const swdft2d_plan_s* p, const void* dy, void* ws, void* dx,
+                               const AdjGeom& g, hipStream_t stream) {
+  hipError_t e = swdft::launch_tree_adj(p->n0, p->n1, real_dtype(p->dtype),
+                                        static_cast<const float2*>(dy), ws, dx, g, p->tw32,
+                                        stream);
+  if (e != hipSuccess) return device_fail(e, "adjoint launch");
+  return SWDFT_OK;
+}
+
+
 }  // namespace host
 }  // namespace swdft
 
@@ -433,34 +468,15 @@ swdft_status_t swdft2d_exec(swdft2d_plan_t plan, const void* x, void* y, hipStre
   return SWDFT_OK;
 }
 
+
 swdft_status_t swdft2d_backward(swdft2d_plan_t plan, const void* dy, void* dx, hipStream_t stream) {
-  if (!is_live(plan)) return fail(SWDFT_E_PLAN, "null or destroyed plan");
-  if (plan->kind == 1) return fail(SWDFT_E_PLAN, "backward is not available for batched plans");
-  if (plan->n0 > SWDFT_MAX_WINDOW_ADJ || plan->n1 > SWDFT_MAX_WINDOW_ADJ || mixed_window(plan))
-    return fail(SWDFT_E_WINDOW, "backward supports power-of-two windows up to %d, not %d x %d",
-                SWDFT_MAX_WINDOW_ADJ, plan->n0, plan->n1);
-  const swdft2d_plan_s* p = plan;
-  const int64_t xb = p->batch * p->N0 * p->N1 * x_elem_bytes(p->dtype);
-  const int64_t yb = swdft2d_output_bytes(plan);
-  swdft_status_t st = check_buffers(p, dy, y_elem_bytes(p->dtype), yb, dx,
-                                    x_elem_bytes(p->dtype), xb, "dy", "dx");
+  swdft::AdjGeom g{};
+  size_t ws_bytes = 0;
+  swdft_status_t st = backward_prepare(plan, dy, dx, &g, &ws_bytes);
   if (st != SWDFT_OK) return st;
-  // The adjoint is always the transposed tree, whichever forward kernel an
-  // AUTO plan ends up running (the tuner may pick the dense variant for the
-  // forward transform; the adjoint of the map x -> y is the same).
-  if (f64_dtype(p->dtype) || (p->algo != SWDFT_ALGO_AUTO && p->algo != SWDFT_ALGO_TREE))
-    return fail(SWDFT_E_DTYPE, "backward runs the transposed tree; it needs an R32/C32 plan "
-                "with the TREE (or AUTO) algorithm");
-  const swdft::AdjGeom g = adj_geom(p);
-  const size_t ws_bytes =
-      (size_t)swdft::tree_adj_workspace_elems(p->n0, p->n1, g) * (real_dtype(p->dtype) ? 4 : 8);
   st = ensure_workspace(plan, ws_bytes);
   if (st != SWDFT_OK) return st;
-  hipError_t e = swdft::launch_tree_adj(p->n0, p->n1, real_dtype(p->dtype),
-                                        static_cast<const float2*>(dy), p->workspace, dx, g,
-                                        p->tw32, stream);
-  if (e != hipSuccess) return device_fail(e, "adjoint launch");
-  return SWDFT_OK;
+  return backward_launch(plan, dy, plan->workspace, dx, g, stream);
 }
 
 swdft_status_t swdft2d_twiddles(swdft2d_plan_t plan, int32_t axis, float* out, int32_t len) {

@@ -133,6 +133,13 @@ int env_int(const char* name, int fallback);  // fallback when unset or empty
 int lds_per_cu();                             // LDS bytes per CU of the current device, 0 if none
 int cu_count();                               // CUs of the current device, 0 if none
 
+// swdft2d_backward in two parts (abi.hip): every check, the launch geometry
+// and the workspace bytes it needs; then the launch with a given workspace.
+swdft_status_t backward_prepare(swdft2d_plan_t plan, const void* dy, void* dx, AdjGeom* g,
+                                size_t* ws_bytes);
+swdft_status_t backward_launch(const swdft2d_plan_s* p, const void* dy, void* ws, void* dx,
+                               const AdjGeom& g, hipStream_t stream);
+
 // tuning cache (tune.hip)
 void apply_cached_tuning(swdft2d_plan_s* p);
 
