@@ -66,6 +66,9 @@ class Oracle:
         lib.oracle_swdft3d.argtypes = [vp, vp, i64, i64, i64, i32, i32, i32, i32, vp, vp, vp,
                                        i64, vp, vp]
         lib.oracle_swdft3d.restype = ctypes.c_int
+        lib.oracle_swdft3d_adjoint.argtypes = [vp, vp, i64, i64, i64, i32, i32, i32, i32, vp, vp,
+                                               vp, i64, vp, vp]
+        lib.oracle_swdft3d_adjoint.restype = ctypes.c_int
         lib.oracle_num_threads.restype = ctypes.c_int
         lib.oracle_set_threads.argtypes = [ctypes.c_int]
         lib.oracle_set_threads.restype = None
@@ -165,6 +168,34 @@ class Oracle:
         y = yr + 1j * yi
         return y.reshape(P0, P1, P2, n0, n1, n2) if windows is None else y
 
+    def swdft3d_adjoint(self, dy, N0: int, N1: int, N2: int, voxels=None,
+                        norm: str = "none") -> np.ndarray:
+        """Explicit 3D adjoint: dy complex [P0, P1, P2, n0, n1, n2] -> dx complex.
+
+        voxels: None -> [N0, N1, N2]; or (r0, r1, r2) int arrays -> [len(r0)].
+        """
+        dy = np.asarray(dy)
+        P0, P1, P2, n0, n1, n2 = dy.shape
+        if (P0, P1, P2) != (N0 - n0 + 1, N1 - n1 + 1, N2 - n2 + 1):
+            raise ValueError("dy shape does not match (N0, N1, N2)")
+        gr = _as_f64(dy.real)
+        gi = _as_f64(dy.imag)
+        if voxels is None:
+            v0 = v1 = v2 = None
+            nvox = N0 * N1 * N2
+        else:
+            v0, v1, v2 = (np.ascontiguousarray(v, dtype=np.int64) for v in voxels)
+            nvox = v0.size
+        dxr = np.empty(nvox, np.float64)
+        dxi = np.empty(nvox, np.float64)
+        rc = self.lib.oracle_swdft3d_adjoint(_ptr(gr), _ptr(gi), N0, N1, N2, n0, n1, n2,
+                                             int(norm == "ortho"), _ptr(v0), _ptr(v1), _ptr(v2),
+                                             nvox, _ptr(dxr), _ptr(dxi))
+        if rc != 0:
+            raise ValueError("oracle_swdft3d_adjoint rejected its arguments")
+        dx = dxr + 1j * dxi
+        return dx.reshape(N0, N1, N2) if voxels is None else dx
+
 
 def get() -> Oracle:
     """The default (unmutated) oracle, compiled on first use if needed."""
@@ -187,3 +218,7 @@ def swdft2d_adjoint(dy, N0, N1, pixels=None, norm="none"):
 
 def swdft3d(x, n0, n1, n2, windows=None, norm="none"):
     return get().swdft3d(x, n0, n1, n2, windows=windows, norm=norm)
+
+
+def swdft3d_adjoint(dy, N0, N1, N2, voxels=None, norm="none"):
+    return get().swdft3d_adjoint(dy, N0, N1, N2, voxels=voxels, norm=norm)

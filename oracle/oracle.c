@@ -332,6 +332,107 @@ int oracle_swdft3d(const double* x_re, const double* x_im, int64_t N0, int64_t N
     return ORACLE_OK;
 }
 
+/*
+ * Adjoint (conjugate transpose) of the 3D forward map above, at a list of
+ * voxels:
+ *
+ *   dx[r0][r1][r2] = s * sum over windows (q0,q1,q2) covering the voxel of
+ *        sum_{k0,k1,k2} dy[q0][q1][q2][k0][k1][k2]
+ *        * conj(W0[((r0-q0) k0) mod n0] * W1[((r1-q1) k1) mod n1] * W2[((r2-q2) k2) mod n2])
+ *
+ *   dy_re, dy_im : cotangent [P0][P1][P2][n0][n1][n2], k2 fastest (all windows).
+ *   v0, v1, v2   : voxel coordinates, nvox entries; all NULL for every voxel in
+ *                  row-major order (nvox = N0*N1*N2).
+ *   dx_re, dx_im : output [nvox] (complex; a real input takes dx_re).
+ */
+int oracle_swdft3d_adjoint(const double* dy_re, const double* dy_im, int64_t N0, int64_t N1,
+                           int64_t N2, int32_t n0, int32_t n1, int32_t n2, int32_t ortho,
+                           const int64_t* v0, const int64_t* v1, const int64_t* v2, int64_t nvox,
+                           double* dx_re, double* dx_im)
+{
+    if (check_shape(N0, N1, n0, n1) != ORACLE_OK || N2 < 1 || n2 < 1 || n2 > N2 || !dy_re ||
+        !dy_im || !dx_re || !dx_im || nvox < 0)
+        return ORACLE_EARG;
+    const int given = (v0 != NULL) + (v1 != NULL) + (v2 != NULL);
+    if (given != 0 && given != 3) return ORACLE_EARG;
+    if (given == 0 && nvox != N0 * N1 * N2) return ORACLE_EARG;
+    if (given == 3) {
+        for (int64_t t = 0; t < nvox; ++t)
+            if (v0[t] < 0 || v0[t] >= N0 || v1[t] < 0 || v1[t] >= N1 || v2[t] < 0 || v2[t] >= N2)
+                return ORACLE_EARG;
+    }
+    const int64_t P0 = N0 - n0 + 1, P1 = N1 - n1 + 1, P2 = N2 - n2 + 1;
+
+    double* w0r = (double*)malloc(sizeof(double) * (size_t)n0);
+    double* w0i = (double*)malloc(sizeof(double) * (size_t)n0);
+    double* w1r = (double*)malloc(sizeof(double) * (size_t)n1);
+    double* w1i = (double*)malloc(sizeof(double) * (size_t)n1);
+    double* w2r = (double*)malloc(sizeof(double) * (size_t)n2);
+    double* w2i = (double*)malloc(sizeof(double) * (size_t)n2);
+    if (!w0r || !w0i || !w1r || !w1i || !w2r || !w2i) {
+        free(w0r); free(w0i); free(w1r); free(w1i); free(w2r); free(w2i);
+        return ORACLE_EARG;
+    }
+    make_twiddles(n0, w0r, w0i);
+    make_twiddles(n1, w1r, w1i);
+    make_twiddles(n2, w2r, w2i);
+    const double scale = ortho ? 1.0 / sqrt((double)n0 * (double)n1 * (double)n2) : 1.0;
+    double conj_sign = -1.0;
+#if ORACLE_MUTATION == 11
+    conj_sign = 1.0; /* mutation: conjugate forgotten */
+#endif
+    int64_t shift1 = 0;
+#if ORACLE_MUTATION == 12
+    shift1 = 1; /* mutation: axis-1 window range off by one */
+#endif
+    const int64_t nk = (int64_t)n0 * n1 * n2;
+
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t t = 0; t < nvox; ++t) {
+        const int64_t r0 = v0 ? v0[t] : t / (N1 * N2);
+        const int64_t r1 = v1 ? v1[t] : (t / N2) % N1;
+        const int64_t r2 = v2 ? v2[t] : t % N2;
+        /* windows with q_i <= r_i <= q_i + n_i - 1 and 0 <= q_i < P_i */
+        int64_t lo0 = r0 - n0 + 1; if (lo0 < 0) lo0 = 0;
+        int64_t hi0 = r0; if (hi0 > P0 - 1) hi0 = P0 - 1;
+        int64_t lo1 = r1 - n1 + 1 + shift1; if (lo1 < 0) lo1 = 0;
+        int64_t hi1 = r1; if (hi1 > P1 - 1) hi1 = P1 - 1;
+        int64_t lo2 = r2 - n2 + 1; if (lo2 < 0) lo2 = 0;
+        int64_t hi2 = r2; if (hi2 > P2 - 1) hi2 = P2 - 1;
+        double acc_r = 0.0, acc_i = 0.0;
+        for (int64_t a0 = lo0; a0 <= hi0; ++a0) {
+            for (int64_t a1 = lo1; a1 <= hi1; ++a1) {
+                for (int64_t a2 = lo2; a2 <= hi2; ++a2) {
+                    const int64_t j0 = r0 - a0, j1 = r1 - a1, j2 = r2 - a2;
+                    const int64_t base = ((a0 * P1 + a1) * P2 + a2) * nk;
+                    for (int k0 = 0; k0 < n0; ++k0) {
+                        for (int k1 = 0; k1 < n1; ++k1) {
+                            for (int k2 = 0; k2 < n2; ++k2) {
+                                const int e0 = (int)((j0 * k0) % n0);
+                                const int e1 = (int)((j1 * k1) % n1);
+                                const int e2 = (int)((j2 * k2) % n2);
+                                /* u = W0[e0] W1[e1], t = conj(u W2[e2]) */
+                                const double ur = w0r[e0] * w1r[e1] - w0i[e0] * w1i[e1];
+                                const double ui = w0r[e0] * w1i[e1] + w0i[e0] * w1r[e1];
+                                const double tr = ur * w2r[e2] - ui * w2i[e2];
+                                const double ti = conj_sign * (ur * w2i[e2] + ui * w2r[e2]);
+                                const int64_t idx = base + ((int64_t)k0 * n1 + k1) * n2 + k2;
+                                const double gr = dy_re[idx], gi = dy_im[idx];
+                                acc_r += gr * tr - gi * ti;
+                                acc_i += gr * ti + gi * tr;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        dx_re[t] = acc_r * scale;
+        dx_im[t] = acc_i * scale;
+    }
+    free(w0r); free(w0i); free(w1r); free(w1i); free(w2r); free(w2i);
+    return ORACLE_OK;
+}
+
 /* Number of threads an OpenMP region of this library would use (1 if built
  * without OpenMP). Reported beside timings of the oracle. */
 #ifdef _OPENMP

@@ -408,8 +408,69 @@ def pin3d_parseval_ortho(orc):
     assert np.array_equal(orc.swdft3d(x, n0, n1, n2, windows=q), y[q])
 
 
+def _forward3d_matrix(N, n):
+    """The 3D forward map as an explicit matrix, built with numpy.fft.fftn of
+    the windows of every unit impulse (no oracle code): column v is the
+    output of the impulse at voxel v, flattened [P0][P1][P2][n0][n1][n2]."""
+    cols = []
+    for v in range(int(np.prod(N))):
+        e = np.zeros(int(np.prod(N)))
+        e[v] = 1.0
+        win = np.lib.stride_tricks.sliding_window_view(e.reshape(N), n)
+        cols.append(np.fft.fftn(win, axes=(-3, -2, -1)).ravel())
+    return np.stack(cols, axis=1)
+
+
+def pin3d_adjoint_matrix(orc):
+    """The 3D adjoint equals the conjugate transpose of the explicit forward
+    matrix (numpy fftn per window) on small volumes, unequal window sides,
+    and with the orthonormal scale."""
+    rng = np.random.default_rng(36)
+    for N, n in [((4, 5, 6), (2, 4, 2)), ((5, 4, 3), (4, 1, 2)), ((3, 6, 5), (1, 2, 4))]:
+        M = _forward3d_matrix(N, n)
+        P = tuple(N[i] - n[i] + 1 for i in range(3))
+        g = rng.standard_normal(P + n) + 1j * rng.standard_normal(P + n)
+        ref = (M.conj().T @ g.ravel()).reshape(N)
+        got = orc.swdft3d_adjoint(g, *N)
+        assert _rel(got, ref) < 1e-13, (N, n)
+        scale = 1.0 / np.sqrt(np.prod(n))
+        assert _rel(orc.swdft3d_adjoint(g, *N, norm="ortho"), ref * scale) < 1e-13
+
+
+def pin3d_adjoint_dot_fd(orc):
+    """<M x, g> = <x, M^H g> against the 3D forward oracle; the quadratic
+    loss L = sum w |M x|^2 has exact central differences (h = 1) equal to
+    Re(M^H (2 w M x)) at every sampled voxel (corners included); sampled
+    voxels equal the same entries of the full adjoint."""
+    rng = np.random.default_rng(37)
+    N, n = (7, 8, 9), (4, 2, 4)
+    P = tuple(N[i] - n[i] + 1 for i in range(3))
+    x = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    g = rng.standard_normal(P + n) + 1j * rng.standard_normal(P + n)
+    lhs = np.vdot(g, orc.swdft3d(x, *n))
+    rhs = np.vdot(orc.swdft3d_adjoint(g, *N), x)
+    assert abs(lhs - rhs) < 1e-11 * max(abs(lhs), 1.0)
+    xr = rng.standard_normal(N)
+    w = (rng.random(n) < 0.3).astype(float)
+    w[0, 1, 1] = 1.0
+
+    def loss(z):
+        return float(np.sum(w * np.abs(orc.swdft3d(z, *n)) ** 2))
+
+    grad = orc.swdft3d_adjoint(2.0 * w * orc.swdft3d(xr, *n), *N).real
+    vox = [(0, 0, 0), (N[0] - 1, N[1] - 1, N[2] - 1), (3, 4, 5), (0, N[1] - 1, 2), (6, 0, 8)]
+    for v in vox:
+        e = np.zeros(N)
+        e[v] = 1.0
+        fd = (loss(xr + e) - loss(xr - e)) / 2.0
+        assert abs(fd - grad[v]) < 1e-10 * max(1.0, abs(fd)), (v, fd, grad[v])
+    vv = tuple(np.array(a) for a in zip(*vox))
+    full = orc.swdft3d_adjoint(g, *N)
+    assert np.array_equal(orc.swdft3d_adjoint(g, *N, voxels=vv), full[vv])
+
+
 PINS_3D = [pin3d_fftn, pin3d_separable, pin3d_exact_small, pin3d_shift_axis2,
-           pin3d_parseval_ortho]
+           pin3d_parseval_ortho, pin3d_adjoint_matrix, pin3d_adjoint_dot_fd]
 
 ALL_PINS = [pin_matrix_form, pin_fft2, pin_mixed_radix, pin_whole_array, pin_exact_small, pin_impulse,
             pin_constant, pin_onbin_exponential, pin_onbin_cosine, pin_parseval,

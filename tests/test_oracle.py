@@ -43,6 +43,8 @@ MUTANTS = {
     8: "3D: last slice of every window dropped",
     9: "3D: k1 and k2 swapped",
     10: "3D: axis-2 roots of the wrong length",
+    11: "3D adjoint without conjugate",
+    12: "3D adjoint axis-1 window range off by one",
 }
 
 
