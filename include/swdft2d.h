@@ -355,6 +355,20 @@ int64_t swdft3d_output_elems(swdft3d_plan_t plan);
 /* Launch shape as text (algorithm, tile, slab, counts). */
 swdft_status_t swdft3d_describe(swdft3d_plan_t plan, char* buf, int32_t len);
 
+/* Adjoint of the 3D map x -> y (its conjugate transpose, the 3D analogue of
+ * swdft2d_backward): dx = M^H dy, Re(M^H dy) for an R32 plan. dy has y's
+ * layout [batch][P0][P1][P2][n0][n1][n2] (complex64), dx has x's layout and
+ * type. The transposed tree levels run in reverse order (axis 0 streamed up
+ * each slab, then axes 1 and 2 per window position), and partial sums per
+ * (window row q1, strip) tile go through a plan-owned workspace (about
+ * n1 (W + n2 - 1) / W times dx, W = 64 / (n1 n2)) allocated at the first
+ * call and freed by swdft3d_destroy; a second kernel adds them in a fixed
+ * order (deterministic). Checks: live plan (E_PLAN); dy, dx non-null (E_ARG),
+ * dy 8-byte and dx element aligned (E_ALIGN), not overlapping (E_ARG);
+ * E_NOMEM when the workspace cannot be allocated. Calls with one plan must
+ * be ordered (they share its workspace). */
+swdft_status_t swdft3d_backward(swdft3d_plan_t plan, const void* dy, void* dx, hipStream_t stream);
+
 /* Free the plan (E_PLAN if already destroyed). NULL is accepted. The caller
  * must not destroy a plan while work it enqueued is in flight. */
 swdft_status_t swdft3d_destroy(swdft3d_plan_t plan);

@@ -340,6 +340,24 @@ class Plan3D:
             self.exec_ptr(x.data_ptr(), out.data_ptr(), stream)
         return out
 
+    def backward(self, dy: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Adjoint: dy [B,P0,P1,P2,n0,n1,n2] complex64 -> dx [B,N0,N1,N2] (x's dtype)."""
+        if dy.dtype != torch.complex64 or tuple(dy.shape) != self.out_shape or \
+                not dy.is_contiguous() or not dy.is_cuda:
+            raise ValueError(f"dy must be a contiguous cuda complex64 tensor of shape "
+                             f"{self.out_shape}")
+        want = (self.batch,) + self.N
+        if out is None:
+            out = torch.empty(want, dtype=self.dtype, device=dy.device)
+        elif (out.dtype != self.dtype or tuple(out.shape) != want or not out.is_contiguous()
+              or out.device != dy.device):
+            raise ValueError("out has the wrong shape, dtype or device")
+        with torch.cuda.device(dy.device):
+            stream = torch.cuda.current_stream(dy.device).cuda_stream
+            check(lib.swdft3d_backward(self.handle, dy.data_ptr(), out.data_ptr(), stream),
+                  "swdft3d_backward")
+        return out
+
     def close(self):
         if getattr(self, "handle", None) is not None:
             check(lib.swdft3d_destroy(self.handle), "swdft3d_destroy")
@@ -413,14 +431,50 @@ def swdft3d(x: torch.Tensor, n0: int, n1: int, n2: int, norm: str = "none") -> t
     squeeze = x.dim() == 3
     xb = x.unsqueeze(0) if squeeze else x
     B, N0, N1, N2 = xb.shape
-    key = ("3d", N0, N1, N2, n0, n1, n2, xb.dtype, B, norm)
+    y = _cached_plan3d(N0, N1, N2, n0, n1, n2, xb.dtype, B, norm).forward(xb)
+    return y[0] if squeeze else y
+
+
+def _cached_plan3d(N0, N1, N2, n0, n1, n2, dtype, batch, norm) -> Plan3D:
+    # per host thread and device stream, like _cached_plan (a plan holds one
+    # adjoint workspace)
+    stream = torch.cuda.current_stream().cuda_stream if torch.cuda.is_available() else 0
+    key = ("3d", N0, N1, N2, n0, n1, n2, dtype, batch, norm, threading.get_ident(),
+           torch.cuda.current_device() if torch.cuda.is_available() else -1, stream)
     with _cache_lock:
         p = _plan_cache.get(key)
         if p is None:
-            p = Plan3D(N0, N1, N2, n0, n1, n2, dtype=xb.dtype, batch=B, norm=norm)
+            p = Plan3D(N0, N1, N2, n0, n1, n2, dtype=dtype, batch=batch, norm=norm)
             _plan_cache[key] = p
-    y = p.forward(xb)
-    return y[0] if squeeze else y
+        return p
+
+
+def swdft3d_backward(dy: torch.Tensor, N0: int, N1: int, N2: int, dtype=torch.float32,
+                     norm: str = "none") -> torch.Tensor:
+    """3D adjoint: dy [B,P0,P1,P2,n0,n1,n2] -> dx [B,N0,N1,N2] (Re of M^H dy for
+    real dtypes)."""
+    squeeze = dy.dim() == 6
+    dyb = dy.unsqueeze(0) if squeeze else dy
+    B, n0, n1, n2 = dyb.shape[0], dyb.shape[4], dyb.shape[5], dyb.shape[6]
+    dx = _cached_plan3d(N0, N1, N2, n0, n1, n2, dtype, B, norm).backward(dyb.contiguous())
+    return dx[0] if squeeze else dx
+
+
+class SWDFT3dFn(torch.autograd.Function):
+    """y = swdft3d(x); the backward pass runs the library's 3D adjoint kernel
+    (Re(M^H gy) for real x, PyTorch's conjugate-Wirtinger convention)."""
+
+    @staticmethod
+    def forward(ctx, x, n0, n1, n2, norm="none"):
+        ctx.meta = (x.shape, x.dtype, n0, n1, n2, norm)
+        return swdft3d(x, n0, n1, n2, norm=norm)
+
+    @staticmethod
+    def backward(ctx, gy):
+        shape, dtype, n0, n1, n2, norm = ctx.meta
+        N0, N1, N2 = shape[-3], shape[-2], shape[-1]
+        dx = swdft3d_backward(gy.contiguous(), N0, N1, N2, dtype=dtype, norm=norm)
+        return dx.reshape(shape), None, None, None, None
 
 
 def swdft2d_backward(dy: torch.Tensor, N0: int, N1: int, dtype=torch.float32, norm: str = "none",

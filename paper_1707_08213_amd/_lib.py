@@ -59,6 +59,7 @@ SIGNATURES = {
     "swdft2d_stream_destroy": (_int, [_vp]),
     "swdft3d_plan": (_int, [_PLAN_P, _i64, _i64, _i64, _i32, _i32, _i32, _int, _i64]),
     "swdft3d_set_norm": (_int, [_vp, _int]),
+    "swdft3d_backward": (_int, [_vp, _vp, _vp, _vp]),
     "swdft3d_exec": (_int, [_vp, _vp, _vp, _vp]),
     "swdft3d_output_elems": (_i64, [_vp]),
     "swdft3d_describe": (_int, [_vp, ctypes.c_char_p, _i32]),

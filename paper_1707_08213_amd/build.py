@@ -28,7 +28,8 @@ SOURCES = ["abi.hip", "abi_noalloc.hip", "abi3d.hip", "abi_stream.hip", "tree3d_
     for t in ("r", "c")] + [f"tree_fwd_n64_{t}.hip" for t in ("r", "c")] + [
     f"tree_fwd_n{n0}_{t}_{n1}.hip" for n0 in (16, 32) for t in ("r", "c") for n1 in (16, 32, 64)] + [
     f"tree_fwd_n64_{t}_{n1}.hip" for t in ("r", "c") for n1 in (16, 32, 64)] + [
-    f"tree3d_fwd_n{n0}_{t}.hip" for n0 in (2, 4, 8, 16) for t in ("r", "c")] + [
+    f"tree3d_fwd_n{n0}_{t}.hip" for n0 in (2, 4, 8, 16) for t in ("r", "c")] + ["tree3d_adj.hip"] + [
+    f"tree3d_adj_n{n0}_{t}.hip" for n0 in (2, 4, 8, 16) for t in ("r", "c")] + [
     f"tree_stream_n{n0}_{t}.hip" for n0 in (1, 2, 4, 8, 16, 32) for t in ("r", "c")] + [
     f"tree_mixed_n{n0}_{t}.hip" for n0 in (3, 6, 9, 12, 24) for t in ("r", "c")]
 

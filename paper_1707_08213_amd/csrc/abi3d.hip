@@ -16,6 +16,9 @@ struct swdft3d_plan_s {
   swdft_dtype_t dtype = SWDFT_R32;
   swdft_norm_t norm = SWDFT_NORM_NONE;
   swdft::Twiddles3F32 tw{};
+  void* workspace = nullptr;  // adjoint partial sums, allocated at the first backward
+  size_t workspace_bytes = 0;
+  int workspace_device = -1;
 };
 
 namespace swdft {
@@ -93,6 +96,40 @@ swdft::Tree3Geom tree3_geom(const swdft3d_plan_s* p) {
   if (g.lds_cu <= 0) g.wpc = 0;
   const int64_t resident = (int64_t)g.wpc * cu_count();
   g.order = (g.wpc > 0 && resident > 0 && tree3_tiles(p, g.S) > resident) ? 1 : 0;
+  return g;
+}
+
+// dx planes per wave of the 3D adjoint: a whole volume depth when the tiles
+// (window rows q1 x strips) already give enough waves; otherwise slabs, each
+// primed by the n0 - 1 window rows below it.
+swdft::Adj3Geom adj3_geom(const swdft3d_plan_s* p) {
+  swdft::Adj3Geom g{};
+  g.N0 = p->N0;
+  g.N1 = p->N1;
+  g.N2 = p->N2;
+  g.P0 = p->P0;
+  g.P1 = p->P1;
+  g.P2 = p->P2;
+  g.y_image_stride = p->P0 * p->P1 * p->P2 * p->n0 * p->n1 * p->n2;
+  g.nstrips = (int32_t)ceil_div(p->P2, tree3_columns_per_wave(p->n1, p->n2));
+  const int cr = tree3_adj_rows_per_chunk(p->n0, p->n1, p->n2);
+  const int64_t columns = p->batch * p->P1 * g.nstrips;
+  const int64_t full = ceil_div(p->N0, cr) * cr;
+  int64_t S = env_int("SWDFT3D_ADJ_SLAB", 0);
+  if (S <= 0) {
+    S = columns >= 1024 ? full : std::max<int64_t>(ceil_div(p->N0 * columns, 2048),
+                                                    8 * (int64_t)(p->n0 - 1));
+  }
+  S = std::max<int64_t>(S, cr);
+  S = std::min<int64_t>(ceil_div(S, cr) * cr, full);
+  g.S = (int32_t)S;
+  g.nslabs = (int32_t)ceil_div(p->N0, g.S);
+  g.batch = (int32_t)p->batch;
+  g.scale = p->norm == SWDFT_NORM_ORTHO
+                ? (float)(1.0 / std::sqrt((double)p->n0 * p->n1 * p->n2))
+                : 1.0f;
+  g.wpc = 0;
+  g.lds_cu = lds_per_cu();
   return g;
 }
 
@@ -193,6 +230,55 @@ swdft_status_t swdft3d_exec(swdft3d_plan_t plan, const void* x, void* y, hipStre
   return SWDFT_OK;
 }
 
+swdft_status_t swdft3d_backward(swdft3d_plan_t plan, const void* dy, void* dx, hipStream_t stream) {
+  if (!is_live3(plan)) return fail(SWDFT_E_PLAN, "null or destroyed 3D plan");
+  swdft3d_plan_s* p = plan;
+  if (!dy) return fail(SWDFT_E_ARG, "dy is null");
+  if (!dx) return fail(SWDFT_E_ARG, "dx is null");
+  const int64_t xe = x_elem_bytes(p->dtype);
+  if ((uintptr_t)dy % 8u) return fail(SWDFT_E_ALIGN, "dy is not 8-byte aligned");
+  if ((uintptr_t)dx % (uintptr_t)xe)
+    return fail(SWDFT_E_ALIGN, "dx is not %lld-byte aligned", (long long)xe);
+  const int64_t xb = p->batch * p->N0 * p->N1 * p->N2 * xe;
+  const int64_t yb = swdft3d_output_elems(plan) * 8;
+  if (ranges_overlap(dy, yb, dx, xb)) return fail(SWDFT_E_ARG, "dy and dx overlap");
+  const swdft::Adj3Geom g = adj3_geom(p);
+  int64_t ws_elems = swdft::tree3_adj_workspace_elems(p->n1, p->n2, g);
+  int64_t ws_bytes = 0;
+  if (!mul_ok(ws_elems, real_dtype(p->dtype) ? 4 : 8, &ws_bytes))
+    return fail(SWDFT_E_OVERFLOW, "adjoint workspace size overflows int64");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return device_fail(e, "hipGetDevice");
+  if (!p->workspace || p->workspace_device != dev || p->workspace_bytes < (size_t)ws_bytes) {
+    if (p->workspace) {
+      // the old buffer may still be read by work in flight
+      e = hipDeviceSynchronize();
+      if (e != hipSuccess) return device_fail(e, "hipDeviceSynchronize");
+      const int cur = dev;
+      if (p->workspace_device >= 0 && p->workspace_device != cur) (void)hipSetDevice(p->workspace_device);
+      (void)hipFree(p->workspace);
+      if (p->workspace_device != cur) (void)hipSetDevice(cur);
+      p->workspace = nullptr;
+      p->workspace_bytes = 0;
+    }
+    void* ptr = nullptr;
+    e = hipMalloc(&ptr, (size_t)ws_bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(SWDFT_E_NOMEM, "3D adjoint workspace of %lld bytes: %s", (long long)ws_bytes,
+                  hipGetErrorString(e));
+    }
+    p->workspace = ptr;
+    p->workspace_bytes = (size_t)ws_bytes;
+    p->workspace_device = dev;
+  }
+  e = swdft::launch_tree3_adj(p->n0, p->n1, p->n2, real_dtype(p->dtype),
+                              static_cast<const float2*>(dy), p->workspace, dx, g, p->tw, stream);
+  if (e != hipSuccess) return device_fail(e, "3D adjoint launch");
+  return SWDFT_OK;
+}
+
 swdft_status_t swdft3d_describe(swdft3d_plan_t plan, char* buf, int32_t len) {
   if (!is_live3(plan)) return fail(SWDFT_E_PLAN, "null or destroyed 3D plan");
   if (!buf || len < 1) return fail(SWDFT_E_ARG, "describe buffer is null or empty");
@@ -216,8 +302,17 @@ swdft_status_t swdft3d_destroy(swdft3d_plan_t plan) {
     if (it == live_plans3().end()) return fail(SWDFT_E_PLAN, "3D plan already destroyed or unknown");
     live_plans3().erase(it);
   }
+  swdft_status_t st = SWDFT_OK;
+  if (plan->workspace) {
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (plan->workspace_device >= 0) (void)hipSetDevice(plan->workspace_device);
+    const hipError_t e = hipFree(plan->workspace);
+    if (cur >= 0) (void)hipSetDevice(cur);
+    if (e != hipSuccess) st = device_fail(e, "3D workspace free");
+  }
   delete plan;
-  return SWDFT_OK;
+  return st;
 }
 
 }  // extern "C"

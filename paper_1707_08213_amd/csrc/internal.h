@@ -65,6 +65,22 @@ struct Tree3Geom {
   int32_t order;           // tile order: 0 = a contiguous range per XCD, 1 = dispatch order
 };
 
+// Geometry of one 3D adjoint launch. One wave owns a strip of window columns
+// along axis 2 at one window row q1 of axis 1, and a slab of S planes of dx;
+// it writes its partial sums for n1 x (QW + n2 - 1) x lines per plane to the
+// workspace.
+struct Adj3Geom {
+  int64_t N0, N1, N2, P0, P1, P2;
+  int64_t y_image_stride;  // float2 between volumes of dy
+  int32_t S;               // dx planes per wave
+  int32_t nstrips;         // ceil(P2 / windows per wave)
+  int32_t nslabs;          // ceil(N0 / S)
+  int32_t batch;
+  float scale;
+  int32_t wpc;             // resident workgroups per CU: 0 = as many as fit
+  int32_t lds_cu;
+};
+
 // One call of a 2D stream: `rows` new input rows after `rows_before` rows.
 struct StreamGeom {
   int64_t N1, P1;
@@ -151,6 +167,13 @@ int tree3_columns_per_wave(int n1, int n2);
 int tree3_rows_per_chunk(int n0, int n1, int n2);
 hipError_t launch_tree3_fwd(int n0, int n1, int n2, bool real_input, const void* x, float2* y,
                             const Tree3Geom& g, const Twiddles3F32& tw, hipStream_t stream);
+
+// 3D adjoint (tree3d_adj.hip)
+int tree3_adj_rows_per_chunk(int n0, int n1, int n2);
+int64_t tree3_adj_workspace_elems(int n1, int n2, const Adj3Geom& g);
+hipError_t launch_tree3_adj(int n0, int n1, int n2, bool real_input, const float2* dy, void* ws,
+                            void* dx, const Adj3Geom& g, const Twiddles3F32& tw,
+                            hipStream_t stream);
 
 hipError_t launch_tree_adj(int n0, int n1, bool real_input, const float2* dy, void* ws, void* dx,
                            const AdjGeom& g, const TwiddlesF32& tw, hipStream_t stream);

@@ -261,9 +261,9 @@ __global__ __launch_bounds__(64) void tree_adj_kernel(const float2* __restrict__
   // zero gradient. The row address is a running scalar value.
   const int64_t g_first = p_top - (N0W - 1) - q0_last;
   const int64_t g_last = min(p_top - (N0W - 1), p_top - r0);
-  const StepSpan lsp{(int)uniform_u32((uint32_t)max<int64_t>(0, g_first)),
-                     (uint32_t)uniform_u32((uint32_t)max<int64_t>(
-                         0, g_last - max<int64_t>(0, g_first) + 1))};
+  const int64_t g_lo = g_first > 0 ? g_first : 0;
+  const StepSpan lsp{(int)uniform_u32((uint32_t)g_lo),
+                     uniform_u32((uint32_t)(g_last >= g_lo ? g_last - g_lo + 1 : 0))};
   uint64_t dy_addr = uniform_u64((uint64_t)(uintptr_t)dystrip +
                                  (uint64_t)(p_top - (N0W - 1)) * row_bytes);
   int gstep = 0;

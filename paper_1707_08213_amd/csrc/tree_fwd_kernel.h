@@ -303,12 +303,16 @@ struct StepSpan {
   uint32_t span;
 };
 
+// Integer clamp (the min/max templates of the device headers may take a
+// detour through double precision).
+__device__ __forceinline__ int64_t clamp_i64(int64_t v, int64_t lo, int64_t hi) {
+  return v < lo ? lo : (v > hi ? hi : v);
+}
+
 __device__ __forceinline__ StepSpan step_span(int64_t crow, int64_t q_begin, int64_t q_end, int lag,
                                               int steps) {
-  const int lo =
-      (int)uniform_u32((uint32_t)max<int64_t>(0, min<int64_t>(q_begin + lag - crow, steps)));
-  const int hi =
-      (int)uniform_u32((uint32_t)max<int64_t>(lo, min<int64_t>(q_end + lag - crow, steps)));
+  const int lo = (int)uniform_u32((uint32_t)clamp_i64(q_begin + lag - crow, 0, steps));
+  const int hi = (int)uniform_u32((uint32_t)clamp_i64(q_end + lag - crow, lo, steps));
   return StepSpan{lo, (uint32_t)(hi - lo)};
 }
 
