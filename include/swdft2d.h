@@ -79,6 +79,9 @@
  *   SWDFT_ADJ_WPC         resident workgroups per CU of swdft2d_backward
  *                         (0 = no cap)
  *   SWDFT_DENSE_SLAB      window rows per workgroup of DENSE_BF16X2
+ *   SWDFT3D_WPC           resident workgroups per CU of swdft3d_exec
+ *   SWDFT3D_SLAB          window rows (axis 0) per workgroup of swdft3d_exec
+ *   SWDFT3D_ADJ_SLAB      dx planes per workgroup of swdft3d_backward
  */
 #ifndef SWDFT2D_H
 #define SWDFT2D_H

@@ -178,10 +178,8 @@ __global__ __launch_bounds__(64) void tree3_adj_kernel(const float2* __restrict_
       float2 v[N2W];
       sfor<0, N2W>([&](auto K) { v[K] = line[K]; });
       row_levels_adj<N2W>(v, tw.w2);
-      const bool keep = (q2_0 + pa_c) < g.P2;
-      sfor<0, N2W>([&](auto K) {
-        line[K] = keep ? v[N2W - 1 - K] : make_float2(0.f, 0.f);
-      });
+      // (windows past the strip's edge read dy = 0 and contribute 0)
+      sfor<0, N2W>([&](auto K) { line[K] = v[N2W - 1 - K]; });
     });
     __syncthreads();
     // overlap-add the strip's windows along axis 2 for each (plane, j1) line
@@ -208,24 +206,24 @@ __global__ __launch_bounds__(64) void tree3_adj_kernel(const float2* __restrict_
   }
 }
 
-// dx[b][r0][r1][r2] = sum over window rows q1 in [r1 - n1 + 1, r1] of axis 1
-// and strips s whose x columns [s*QW, s*QW + QW + n2 - 1) contain r2 of
-// ws[b][q1][s][r0][r1 - q1][r2 - s*QW], in ascending (q1, s).
+// dx[b][v0][v1][v2] = sum over window rows a in [v1 - n1 + 1, v1] of axis 1
+// and strips s whose x columns [s*QW, s*QW + QW + n2 - 1) contain v2 of
+// ws[b][a][s][v0][v1 - a][v2 - s*QW], in ascending (a, s). One workgroup per
+// (volume line (b, v0, v1), block of columns v2).
 template <int N1W, int N2W, bool REAL>
-__global__ __launch_bounds__(256) void tree3_adj_reduce_kernel(const void* __restrict__ wsv,
-                                                               void* __restrict__ dxv, Adj3Geom g) {
+__global__ __launch_bounds__(tree::kAdjReduceThreads) void tree3_adj_reduce_kernel(
+    const void* __restrict__ wsv, void* __restrict__ dxv, Adj3Geom g, int cblocks) {
   constexpr int QW = 64 / (N1W * N2W);
   constexpr int WCOLS = QW + N2W - 1;
   constexpr int WROW = N1W * WCOLS;
-  const int64_t total = (int64_t)g.batch * g.N0 * g.N1 * g.N2;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  const int64_t v2 = i % g.N2;
-  int64_t rest = i / g.N2;
-  const int64_t v1 = rest % g.N1;
-  rest /= g.N1;
-  const int64_t v0 = rest % g.N0;
-  const int64_t b = rest / g.N0;
+  const int64_t line = (int64_t)blockIdx.x / cblocks;  // (b * N0 + v0) * N1 + v1
+  const int cb = (int)(blockIdx.x - line * cblocks);
+  const int64_t v2 = (int64_t)cb * tree::kAdjReduceThreads + threadIdx.x;
+  if (v2 >= g.N2) return;
+  const int64_t v1 = line % g.N1;
+  const int64_t bv0 = line / g.N1;
+  const int64_t v0 = bv0 % g.N0;
+  const int64_t b = bv0 / g.N0;
   int64_t a_lo = v1 - (N1W - 1);
   a_lo = a_lo > 0 ? a_lo : 0;
   const int64_t a_hi = v1 < g.P1 - 1 ? v1 : g.P1 - 1;
@@ -245,10 +243,11 @@ __global__ __launch_bounds__(256) void tree3_adj_reduce_kernel(const void* __res
       }
     }
   }
+  const int64_t out = line * g.N2 + v2;
   if constexpr (REAL) {
-    reinterpret_cast<float*>(dxv)[i] = acc.x;
+    reinterpret_cast<float*>(dxv)[out] = acc.x;
   } else {
-    reinterpret_cast<float2*>(dxv)[i] = acc;
+    reinterpret_cast<float2*>(dxv)[out] = acc;
   }
 }
 
@@ -263,9 +262,10 @@ hipError_t launch3_adj_one(const float2* dy, void* ws, void* dx, const Adj3Geom&
                      stream, dy, ws, g, tw);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t total = (int64_t)g.batch * g.N0 * g.N1 * g.N2;
+  const int cblocks = (int)((g.N2 + tree::kAdjReduceThreads - 1) / tree::kAdjReduceThreads);
   hipLaunchKernelGGL((tree3_adj_reduce_kernel<N1W, N2W, REAL>),
-                     dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, ws, dx, g);
+                     dim3((unsigned)((int64_t)g.batch * g.N0 * g.N1 * cblocks)),
+                     dim3(tree::kAdjReduceThreads), 0, stream, ws, dx, g, cblocks);
   return hipGetLastError();
 }
 

@@ -320,10 +320,8 @@ __global__ __launch_bounds__(64) void tree_adj_kernel(const float2* __restrict__
       sfor<0, N1W>([&](auto K) { v[K] = zrow[K]; });
       row_levels_adj<N1W>(v, tw.w1);
       // contribution to column q1_0 + rp_c + j is v[n1-1-j]; keep it in place
-      const bool keep = (q1_0 + rp_c) < g.P1;
-      sfor<0, N1W>([&](auto K) {
-        zrow[K] = keep ? v[N1W - 1 - K] : make_float2(0.f, 0.f);
-      });
+      // (window columns past the right edge read dy = 0 and contribute 0)
+      sfor<0, N1W>([&](auto K) { zrow[K] = v[N1W - 1 - K]; });
       __syncthreads();
       // overlap-add the QW window columns of each row: QW + n1 - 1 partial sums
       for (int o = lane; o < C::R * C::WCOLS; o += 64) {
@@ -352,35 +350,54 @@ __global__ __launch_bounds__(64) void tree_adj_kernel(const float2* __restrict__
 }
 
 // dx[b][r][c] = sum over strips s whose columns [s*QW, s*QW + QW + n1 - 1)
-// contain c of ws[b][s][r][c - s*QW], in ascending s.
+// contain c of ws[b][s][r][c - s*QW], in ascending s. One workgroup per
+// (image row, block of kAdjReduceThreads columns): the row comes from the
+// workgroup index (scalar arithmetic), each lane takes one column.
+constexpr int kAdjReduceThreads = 256;
+
 template <int QW, int N1W, bool REAL>
-__global__ __launch_bounds__(256) void tree_adj_reduce_kernel(const void* __restrict__ wsv,
-                                                              void* __restrict__ dxv, AdjGeom g) {
+__global__ __launch_bounds__(kAdjReduceThreads) void tree_adj_reduce_kernel(
+    const void* __restrict__ wsv, void* __restrict__ dxv, AdjGeom g, int cblocks) {
   constexpr int WCOLS = QW + N1W - 1;
-  const int64_t total = (int64_t)g.batch * g.N0 * g.N1;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  const int64_t cidx = i % g.N1;
-  const int64_t rest = i / g.N1;
-  const int64_t r = rest % g.N0;
-  const int64_t b = rest / g.N0;
-  int64_t s_lo = cidx - (WCOLS - 1);
+  const int row = (int)blockIdx.x / cblocks;          // b * N0 + r
+  const int cb = (int)blockIdx.x - row * cblocks;
+  const int64_t c = (int64_t)cb * kAdjReduceThreads + threadIdx.x;
+  if (c >= g.N1) return;
+  const int b = row / (int)g.N0;
+  const int r = row - b * (int)g.N0;
+  int64_t s_lo = c - (WCOLS - 1);
   s_lo = s_lo > 0 ? (s_lo + QW - 1) / QW : 0;
-  int64_t s_hi = cidx / QW;
+  int64_t s_hi = c / QW;
   if (s_hi > g.nstrips - 1) s_hi = g.nstrips - 1;
-  if constexpr (REAL) {
-    const float* ws = reinterpret_cast<const float*>(wsv);
-    float acc = 0.f;
-    for (int64_t s = s_lo; s <= s_hi; ++s)
-      acc += ws[((b * g.nstrips + s) * g.N0 + r) * WCOLS + (cidx - s * QW)];
-    reinterpret_cast<float*>(dxv)[i] = acc;
-  } else {
-    const float2* ws = reinterpret_cast<const float2*>(wsv);
-    float2 acc = make_float2(0.f, 0.f);
-    for (int64_t s = s_lo; s <= s_hi; ++s)
-      acc = cadd(acc, ws[((b * g.nstrips + s) * g.N0 + r) * WCOLS + (cidx - s * QW)]);
-    reinterpret_cast<float2*>(dxv)[i] = acc;
-  }
+  // ws index of (b, s, r, c - s*QW): base + s * (N0 * WCOLS - QW). At most
+  // NS strips cover a column; their loads are issued together (unrolled,
+  // the ones past s_hi predicated off) and added in ascending s.
+  constexpr int NS = (WCOLS + QW - 1) / QW;
+  const int64_t step = g.N0 * WCOLS - QW;
+  const int64_t idx0 = (((int64_t)b * g.nstrips + s_lo) * g.N0 + r) * WCOLS + (c - s_lo * QW);
+  const int cnt = (int)(s_hi - s_lo + 1);
+  const int64_t out = (int64_t)row * g.N1 + c;
+  using T = std::conditional_t<REAL, float, float2>;
+  const T* ws = reinterpret_cast<const T*>(wsv);
+  T part[NS];
+  sfor<0, NS>([&](auto K) {
+    constexpr int k = K;
+    const T v = ws[idx0 + (k < cnt ? k : 0) * step];  // in range for every k
+    if constexpr (REAL) {
+      part[k] = k < cnt ? v : 0.f;
+    } else {
+      part[k] = k < cnt ? v : make_float2(0.f, 0.f);
+    }
+  });
+  T acc = part[0];
+  sfor<1, NS>([&](auto K) {
+    if constexpr (REAL) {
+      acc += part[K];
+    } else {
+      acc = cadd(acc, part[K]);
+    }
+  });
+  reinterpret_cast<T*>(dxv)[out] = acc;
 }
 
 template <int N0W, int N1W, bool REAL, int KG>
@@ -394,9 +411,10 @@ hipError_t launch_adj_kg(const float2* dy, void* ws, void* dx, const AdjGeom& g,
                      stream, dy, ws, g, tw);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t total = (int64_t)g.batch * g.N0 * g.N1;
+  const int cblocks = (int)((g.N1 + kAdjReduceThreads - 1) / kAdjReduceThreads);
   hipLaunchKernelGGL((tree_adj_reduce_kernel<C::QW, N1W, REAL>),
-                     dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, ws, dx, g);
+                     dim3((unsigned)((int64_t)g.batch * g.N0 * cblocks)), dim3(kAdjReduceThreads),
+                     0, stream, ws, dx, g, cblocks);
   return hipGetLastError();
 }
 

@@ -506,3 +506,17 @@ def test_twiddles_argument_checks():
     finally:
         lib.swdft2d_destroy(h)
     assert lib.swdft2d_twiddles(None, 0, buf, 64) == S["SWDFT_E_PLAN"]
+
+
+def test_every_environment_variable_is_documented():
+    """Each environment variable the library reads appears in the header's
+    list of environment variables."""
+    import glob
+    names = set()
+    for path in glob.glob(os.path.join(ROOT, "paper_1707_08213_amd", "csrc", "*.hip")):
+        text = open(path).read()
+        names |= set(re.findall(r'(?:getenv|env_int)\(\s*"(SWDFT[A-Z0-9_]*)"', text))
+    assert "SWDFT_TREE_KG" in names and "SWDFT_AUTOTUNE_CACHE" in names
+    header = open(os.path.join(ROOT, "include", "swdft2d.h")).read()
+    missing = sorted(n for n in names if not re.search(r"\*\s+" + n + r"\s", header))
+    assert not missing, f"environment variables read but not documented: {missing}"
