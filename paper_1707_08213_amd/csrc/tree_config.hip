@@ -52,12 +52,13 @@ bool small_image(const swdft2d_plan_s* p) {
   return strips * slabs * p->batch < ncu;
 }
 
-// Split and waves per strip for small images (100 x 100: 32 x 32 split over
-// two lanes and two waves 50.8 -> 31.8 us; 8 x 8 unsplit 6.9 -> 5.7 us).
+// Split and waves per strip for small images: as many residues per stream as
+// are built (two lanes, and two waves where they exist), so that each step of
+// a wave's walk down its short slab is short; the time of a small image is
+// that of the walks (slab rows + n0 - 1 priming rows), not of the output
+// stream.
 int small_image_kg(int n0, int n1, int kg) {
-  if (n0 == 32 && n1 == 32) return 2;
-  if (n0 == 8 && n1 == 8) return 1;
-  return kg;
+  return n0 < 64 && swdft::tree_fwd_kg_supported(n0, n1, 2) ? 2 : kg;
 }
 
 int32_t tree_kg(const swdft2d_plan_s* p) {
@@ -116,6 +117,8 @@ TreeCap tree_cap(const swdft2d_plan_s* p, int kg) {
   c.wpc = p->tree_wpc >= 0 ? p->tree_wpc : env_int("SWDFT_TREE_WPC", -1);
   if (c.wpc < 0) {
     c.wpc = 0;
+    // small images: no cap, their many short tiles run at once
+    if (small_image(p) && !mixed_window(p) && p->n0 < 64) return c;
     // one resident workgroup per CU for the shapes above; two for the others
     // (1024 x 1024, alternating A/B: 8 x 8 102 -> 85-92 us, 8 x 16 198 -> 193 us), and for
     // mixed-radix windows of 12 x 12 and up (12 x 12 259 -> 246 us, 24 x 24
@@ -151,7 +154,7 @@ int32_t tree_wv(const swdft2d_plan_s* p, int kg, int wpc) {
   int wv = p->tree_wv > 0 ? p->tree_wv : env_int("SWDFT_TREE_WV", 0);
   if (wv <= 0) {
     wv = (wpc == 1 && two_waves_by_default(p->n0, p->n1, kg)) ? 2 : 1;
-    if (small_image(p) && p->n0 == 32 && p->n1 == 32 && kg == 2) wv = 2;
+    if (small_image(p) && p->n0 < 64 && swdft::tree_fwd_wv_supported(p->n0, kg, 2)) wv = 2;
   }
   if (!swdft::tree_fwd_wv_supported(p->n0, kg, wv)) wv = 1;
   if (!swdft::tree_fwd_wv_supported(p->n0, kg, wv)) wv = 2;  // n0 = 64 unsplit: two waves only
@@ -166,6 +169,28 @@ int32_t tree_slab(const swdft2d_plan_s* p, int kg, int wv, const TreeCap& cap) {
   const int cr = tree_chunk_rows(p, kg, wv);
   const int64_t nstrips = ceil_div(p->P1, swdft::tree_fwd_columns_per_wave(p->n0, p->n1, kg));
   int64_t S = p->tree_slab > 0 ? p->tree_slab : env_int("SWDFT_TREE_SLAB", 0);
+  if (small_image(p) && !mixed_window(p) && p->n0 < 64) {
+    // Small images: a wave's time is its walk of S + n0 - 1 rows (the slab and
+    // the priming rows above it), and with more tiles than SIMDs the tiles
+    // queue. S minimises (S + n0 - 1 + F) * max(1, waves / SIMDs), F a
+    // per-tile cost in rows (row phase and set-up). A slab need not be a
+    // whole number of chunks (long chunks skip the steps past its end).
+    if (S <= 0) {
+      const int64_t simds = 4 * (cu_count() > 0 ? cu_count() : 256);
+      constexpr int64_t kTileRows = 8;
+      double best = 0.0;
+      for (int64_t s = 1; s <= p->P0; ++s) {
+        const int64_t waves = nstrips * ceil_div(p->P0, s) * p->batch * wv;
+        const double t = (double)(s + p->n0 - 1 + kTileRows) *
+                         std::max(1.0, (double)waves / (double)simds);
+        if (S <= 0 || t < best) {
+          S = s;
+          best = t;
+        }
+      }
+    }
+    return (int32_t)std::min<int64_t>(S, p->P0);
+  }
   if (S <= 0) {
     if (cap.wpc > 0 && cap.slabs > 0) {
       S = ceil_div(p->P0, cap.slabs);

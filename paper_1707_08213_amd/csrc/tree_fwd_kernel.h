@@ -523,18 +523,34 @@ __device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float
     const StepSpan sp = step_span(crow, row0, q0_end, N0W - 1, C::CR);
     uint64_t row_addr = uniform_u64((uint64_t)(uintptr_t)ystrip +
                                     (uint64_t)(crow - (N0W - 1)) * row_bytes);
-    sfor<0, C::CR>([&](auto STc) {
-      constexpr int st = STc;
-      if constexpr (st + kLdsAhead < C::CR) zq[st + kLdsAhead] = zcol[(st + kLdsAhead) * C::ZROW];
-      __builtin_amdgcn_sched_barrier(0);  // keep the read ahead of this step's work
-      const float2 z = zq[st];
-      const auto out = step_rsrc(row_addr, st, sp, strip_bytes);
-      row_addr += row_bytes;
-      if constexpr (N0W == 1) {
-        store_buf<C::NT_STORES>(out, lane_off, z);
-      } else {
-        column_levels<N0W, C::KT, st % C::RING>(z, ring, lanefac, lw, w0, [&](auto J, float2 v) {
-          store_buf<C::NT_STORES>(out, lane_off + (C::KT * J) * N1W * (int)sizeof(float2), v);
+    // Steps past the slab's last row (in its last chunk; the short slabs of
+    // small images end early in their only chunk) would only prime rings that
+    // are never used. Long chunks (CR >= 32 rows, the split and multi-wave
+    // tiles) skip them in blocks of SB steps with a uniform branch; short
+    // chunks run whole (a branch per few light steps measurably slowed them:
+    // 1024^2 / 8 x 8, 90 -> 97 us).
+    constexpr bool kSkip = C::CR >= 32;
+    constexpr int SB = kSkip ? 8 : C::CR;
+    const int live = kSkip ? min(C::CR, nrows - c * C::CR) : C::CR;
+    sfor<0, C::CR / SB>([&](auto BLK) {
+      if (!kSkip || BLK * SB < live) {
+        sfor<0, SB>([&](auto SS) {
+          constexpr int st = BLK * SB + SS;
+          if constexpr (st + kLdsAhead < C::CR)
+            zq[st + kLdsAhead] = zcol[(st + kLdsAhead) * C::ZROW];
+          __builtin_amdgcn_sched_barrier(0);  // keep the read ahead of this step's work
+          const float2 z = zq[st];
+          const auto out = step_rsrc(row_addr, st, sp, strip_bytes);
+          row_addr += row_bytes;
+          if constexpr (N0W == 1) {
+            store_buf<C::NT_STORES>(out, lane_off, z);
+          } else {
+            column_levels<N0W, C::KT, st % C::RING>(
+                z, ring, lanefac, lw, w0, [&](auto J, float2 v) {
+                  store_buf<C::NT_STORES>(out, lane_off + (C::KT * J) * N1W * (int)sizeof(float2),
+                                          v);
+                });
+          }
         });
       }
     });
@@ -571,8 +587,11 @@ inline unsigned occupancy_lds(int wpc, int lds_cu, unsigned static_lds) {
 }
 
 // Two waves per strip exist for n0 >= 16 (where one wave per CU is the
-// default and the wave's issue rate bounds the tile).
-constexpr bool tree_has_wv2(int n0, int kg) { return n0 >= 16 && kg * 2 < n0; }
+// default and the wave's issue rate bounds the tile), and for n0 = 8 with
+// two-lane streams (small images: four residues per stream).
+constexpr bool tree_has_wv2(int n0, int kg) {
+  return (n0 >= 16 && kg * 2 < n0) || (n0 == 8 && kg == 2);
+}
 
 // Lanes per stream of the n0 = 64 kernels: as many as one wave's 64 lanes
 // allow (n1 * KG <= 64), at most 8. The register rings then hold 68 (KG = 8),

@@ -349,13 +349,17 @@ def test_window64_limits_of_other_paths():
 
 
 @pytest.mark.parametrize("N,n,slab,slabs", [
-    (100, 16, 16, 6),     # 22 strips: one-chunk slabs rather than 44 long ones
-    (100, 32, 128, 1),    # split streams on two waves: 128-row chunks
+    (100, 16, 8, 11),     # 43 two-lane strips x 11 slabs of 8 rows: 946 waves
+    (100, 32, 10, 7),     # 69 strips x 7 slabs of 10 rows (not whole 128-row chunks)
+    (100, 8, 5, 19),      # 24 strips x 19 slabs of 5 rows
+    (100, 64, 128, 1),    # n0 = 64 keeps whole columns (one 128-row chunk)
     (1024, 16, 1024, 1),  # one workgroup per CU walking whole columns
 ])
 def test_tree_slab_rule(N, n, slab, slabs):
-    """Small images take one-chunk slabs when longer slabs would leave fewer
-    tiles than compute units (256 assumed without a device)."""
+    """Small images (fewer tiles than compute units with one-chunk slabs;
+    256 assumed without a device) take two-lane streams on two waves and the
+    slab S that minimises (S + n0 - 1 + 8) * max(1, waves / SIMDs); larger
+    images keep their whole-column or about-4096-tile rules."""
     st, h = make_plan(N, N, n, n)
     assert st == 0
     buf = ctypes.create_string_buffer(512)
@@ -398,12 +402,14 @@ def test_mixed_radix_plan_rules():
         S["SWDFT_E_NOT_POW2"]
 
 
-@pytest.mark.parametrize("N,n,kg,wv", [(100, 32, 2, 2), (100, 8, 1, 1), (100, 16, 1, 1),
+@pytest.mark.parametrize("N,n,kg,wv", [(100, 32, 2, 2), (100, 8, 2, 2), (100, 16, 2, 2),
+                                       (100, 4, 1, 1), (100, 64, 1, 2),
                                        (1024, 32, 1, 2), (1024, 8, 2, 1)])
 def test_tree_small_image_split(N, n, kg, wv):
-    """Small images (fewer tiles than compute units) split 32 x 32 streams over
-    two lanes and two waves and keep 8 x 8 streams whole; large images keep
-    the large-image defaults."""
+    """Small images (fewer tiles than compute units) split their streams over
+    two lanes and two waves where those kernels exist (n0 = 8 to 32), so each
+    step of a short walk is short; large images keep the large-image
+    defaults."""
     st, h = make_plan(N, N, n, n)
     assert st == 0
     buf = ctypes.create_string_buffer(512)

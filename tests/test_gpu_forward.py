@@ -317,3 +317,20 @@ def test_default_launch_1024_sampled(swd, orc, n0, n1):
     torch.cuda.empty_cache()
     ref = orc.swdft2d(x.astype(np.float64), n0, n1, windows=(q0, q1))
     assert rel_err(got, ref) <= TOL_F32
+
+
+@pytest.mark.parametrize("n", [4, 8, 16, 32, 64])
+def test_tree_fig4_size_short_slabs(swd, orc, n):
+    """The Fig. 4 array size (100 x 100, square windows): small images take
+    short slabs that are not whole chunks (the steps past a slab's last row
+    are skipped) and split streams; real and complex input, a batch of two,
+    against the oracle on every window."""
+    x = workloads.normal_real((2, 100, 100), seed=900 + n)
+    xc = workloads.normal_complex((100, 100), seed=950 + n)
+    plan = swd.Plan(100, 100, n, n, torch.float32, batch=2)
+    print(f"[case] fig4 size n={n} {plan.describe()}", flush=True)
+    y = plan.forward(torch.from_numpy(x).cuda()).cpu().numpy()
+    for b in range(2):
+        assert rel_err(y[b], orc.swdft2d(x[b].astype(np.float64), n, n)) <= TOL_F32
+    yc = gpu_full(swd, xc, n, n)
+    assert rel_err(yc, orc.swdft2d(xc.astype(np.complex128), n, n)) <= TOL_F32
