@@ -99,6 +99,18 @@ def test_stream_complex_ortho_and_reset(swd, orc):
     assert torch.equal(torch.view_as_real(y2), torch.view_as_real(y))
 
 
+@pytest.mark.parametrize("n0,n1", [(4, 4), (4, 16), (2, 8), (16, 4)], ids=lambda v: str(v))
+def test_stream_complex_split_streams(swd, orc, n0, n1):
+    """Complex input through the split streams of small n0 (from n0 = 4 on a
+    stream spans two lanes): random push sizes against the oracle."""
+    x = workloads.normal_complex((2 * n0 + 41, 3 * (64 // n1) + n1 + 2), seed=610 + 8 * n0 + n1)
+    chunks = chunk_list(x.shape[0], 7 * n0 + n1)
+    print(f"[case] complex stream n={n0}x{n1} chunks={chunks[:8]}...", flush=True)
+    _, y = stream_all(swd, x, n0, n1, chunks)
+    ref = orc.swdft2d(x.astype(np.complex128), n0, n1)
+    assert rel_err(y.cpu().numpy(), ref) <= TOL
+
+
 def test_stream_short_pushes_emit_nothing_until_a_window_completes(swd):
     n0, n1 = 16, 8
     s = swd.Stream2D(40, n0, n1)
