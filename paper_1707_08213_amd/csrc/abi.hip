@@ -441,12 +441,13 @@ swdft_status_t swdft2d_exec(swdft2d_plan_t plan, const void* x, void* y, hipStre
       if (mixed_window(p)) {
         e = real_dtype(p->dtype)
                 ? swdft::launch_tree_mixed_r(p->n0, p->n1, x, static_cast<float2*>(y),
-                                             tree_geom(p), p->tw32, stream)
+                                             tree_geom_cached(plan), p->tw32, stream)
                 : swdft::launch_tree_mixed_c(p->n0, p->n1, x, static_cast<float2*>(y),
-                                             tree_geom(p), p->tw32, stream);
+                                             tree_geom_cached(plan), p->tw32, stream);
       } else {
         e = swdft::launch_tree_fwd(p->n0, p->n1, real_dtype(p->dtype), x,
-                                   static_cast<float2*>(y), tree_geom(p), p->tw32, stream);
+                                   static_cast<float2*>(y), tree_geom_cached(plan), p->tw32,
+                                   stream);
       }
       break;
     case SWDFT_ALGO_DENSE_BF16X2:

@@ -71,6 +71,13 @@ struct swdft2d_plan_s {
   int32_t tree_wpc = -1;                      // resident workgroups per CU, -1 = automatic
   int32_t tree_wv = 0;                        // waves per strip (1 or 2), 0 = automatic
   int32_t dense_slab = 0;                     // 0 = choose automatically
+  // Forward tree launch shape of the last exec and the inputs it was derived
+  // from (device, the plan's tree_* choices, norm, SWDFT_TREE_* values): the
+  // derivation costs about a microsecond of host time, as much as a small
+  // image's kernel.
+  bool tree_geom_valid = false;
+  int32_t tree_geom_key[10] = {};
+  swdft::TreeGeom tree_geom_last{};
   swdft::TwiddlesF32 tw32{};
   swdft::TwiddlesF64 tw64{};
   void* workspace = nullptr;
@@ -114,6 +121,9 @@ void make_twiddles_f32(int n, float2* w);
 float norm_scale(swdft_norm_t norm, int n0, int n1);
 swdft_algo_t resolve_algo(const swdft2d_plan_s* p);
 TreeGeom tree_geom(const swdft2d_plan_s* p);
+// tree_geom(p), derived again only when one of its inputs changed since the
+// plan's last call.
+const TreeGeom& tree_geom_cached(swdft2d_plan_s* p);
 // Rows per chunk of the plan's tree kernel (radix-2 or mixed-radix).
 int tree_chunk_rows(const swdft2d_plan_s* p, int kg, int wv);
 DenseGeom dense_geom(const swdft2d_plan_s* p);

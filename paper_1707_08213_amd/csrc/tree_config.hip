@@ -252,5 +252,26 @@ swdft::TreeGeom tree_geom(const swdft2d_plan_s* p) {
   return g;
 }
 
+const swdft::TreeGeom& tree_geom_cached(swdft2d_plan_s* p) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+  const int32_t key[10] = {dev,
+                           p->tree_kg,
+                           p->tree_wpc,
+                           p->tree_wv,
+                           p->tree_slab,
+                           (int32_t)p->norm,
+                           env_int("SWDFT_TREE_KG", 0),
+                           env_int("SWDFT_TREE_WPC", -1),
+                           env_int("SWDFT_TREE_WV", 0),
+                           env_int("SWDFT_TREE_SLAB", 0)};
+  if (!p->tree_geom_valid || !std::equal(key, key + 10, p->tree_geom_key)) {
+    p->tree_geom_last = tree_geom(p);
+    std::copy(key, key + 10, p->tree_geom_key);
+    p->tree_geom_valid = true;
+  }
+  return p->tree_geom_last;
+}
+
 }  // namespace host
 }  // namespace swdft

@@ -107,6 +107,15 @@ __device__ __forceinline__ T uniform_copy(const T& src) {
   return __builtin_bit_cast(T, out);
 }
 
+// a * b for complex a, b with every rounding written out: each part is one
+// rounded product fed to one fused multiply-add, so that no choice is left
+// to the compiler's contraction and every inlined copy of a butterfly (the
+// unrolled steps of a chunk, the priming steps of a slab's first chunk, the
+// other kernels that share these levels) rounds the same way.
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(__builtin_fmaf(a.x, b.x, -(a.y * b.y)), __builtin_fmaf(a.x, b.y, a.y * b.x));
+}
+
 // d * Omega[IDX] for a length-N twiddle vector, IDX < N/2 known at compile
 // time. Omega[0] = 1 and Omega[N/4] = -i are applied exactly without a
 // multiply; every other value comes from the FP64-generated table.
@@ -117,8 +126,7 @@ __device__ __forceinline__ float2 twmul(float2 d, const float2* w) {
   } else if constexpr (4 * IDX == N) {
     return make_float2(d.y, -d.x);
   } else {
-    const float2 t = uload(w + IDX);
-    return make_float2(t.x * d.x - t.y * d.y, t.x * d.y + t.y * d.x);
+    return cmul(uload(w + IDX), d);
   }
 }
 
@@ -177,10 +185,6 @@ struct ColCfg {
   static constexpr int LW = N0W / 2 > 0 ? N0W / 2 : 1;  // held(u - 1) <= n0 / 2
 };
 
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-
 // Column levels u = 1..m0 (Eq. (6)) for one new row p of a (q1, k1) stream:
 //   T_u[p][i]     = T_{u-1}[p - s_u][i] + Omega0[i s_u] T_{u-1}[p][i]
 //   T_u[p][i + h] = T_{u-1}[p - s_u][i] - Omega0[i s_u] T_{u-1}[p][i]
@@ -193,7 +197,14 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 // Where the uniform twiddle is not 1 or -i the product is precomputed per
 // lane (lw[u][j]), so every node costs one complex multiply.
 // emit(j, v) receives output k0 = r + KG j.
-template <int N0W, int KG, int ST, typename Emit>
+//
+// T0 >= 0 marks row p as the T0-th row of a slab whose first window starts
+// at that slab's first row. Level u of row p is then used by some window of
+// the slab only if T0 >= n0 - s_u (it feeds the windows ending at rows p to
+// p + s_u - 1), so the priming rows T0 < n0 - 1 compute only those levels,
+// keep in the ring only the level values a later used node reads, and emit
+// nothing. T0 = -1 computes every level.
+template <int N0W, int KG, int ST, int T0 = -1, typename Emit>
 __device__ __forceinline__ void column_levels(float2 z, float2 (&ring)[ColCfg<N0W, KG>::RING_TOTAL],
                                               const float2 (&lanefac)[ColCfg<N0W, KG>::M0 + 1],
                                               const float2 (&lw)[ColCfg<N0W, KG>::M0 + 1][ColCfg<N0W, KG>::LW],
@@ -206,13 +217,19 @@ __device__ __forceinline__ void column_levels(float2 z, float2 (&ring)[ColCfg<N0
     constexpr int s = N0W >> u;
     constexpr int hp = CC::held(u - 1);
     constexpr int base = CC::ring_off(u) + (ST % s) * hp;
-    if constexpr (u <= CC::G) {
+    constexpr bool level_in = T0 < 0 || T0 >= N0W - (N0W >> (u - 1));  // level u-1 used
+    constexpr bool level_out = T0 < 0 || T0 >= N0W - s;                 // level u used
+    if constexpr (!level_in) {
+      // nothing of this level or above is used at this row
+    } else if constexpr (!level_out) {
+      // level u-1 is read again s_u rows later; level u is not needed yet
+      sfor<0, hp>([&](auto J) { ring[base + J] = cur[J]; });
+    } else if constexpr (u <= CC::G) {
       // one node per lane: i_u = r mod 2^u from i_{u-1} = r mod 2^{u-1}
       const float2 b = ring[base];
       const float2 d = cur[0];
       ring[base] = d;
-      const float2 f = lanefac[u];
-      cur[0] = make_float2(b.x + (f.x * d.x - f.y * d.y), b.y + (f.x * d.y + f.y * d.x));
+      cur[0] = cadd(b, cmul(lanefac[u], d));
     } else {
       float2 nxt[N0W];
       sfor<0, hp>([&](auto J) {
@@ -532,28 +549,46 @@ __device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float
     constexpr bool kSkip = C::CR >= 32;
     constexpr int SB = kSkip ? 8 : C::CR;
     const int live = kSkip ? min(C::CR, nrows - c * C::CR) : C::CR;
-    sfor<0, C::CR / SB>([&](auto BLK) {
-      if (!kSkip || BLK * SB < live) {
-        sfor<0, SB>([&](auto SS) {
-          constexpr int st = BLK * SB + SS;
-          if constexpr (st + kLdsAhead < C::CR)
-            zq[st + kLdsAhead] = zcol[(st + kLdsAhead) * C::ZROW];
-          __builtin_amdgcn_sched_barrier(0);  // keep the read ahead of this step's work
-          const float2 z = zq[st];
-          const auto out = step_rsrc(row_addr, st, sp, strip_bytes);
-          row_addr += row_bytes;
-          if constexpr (N0W == 1) {
-            store_buf<C::NT_STORES>(out, lane_off, z);
-          } else {
-            column_levels<N0W, C::KT, st % C::RING>(
-                z, ring, lanefac, lw, w0, [&](auto J, float2 v) {
-                  store_buf<C::NT_STORES>(out, lane_off + (C::KT * J) * N1W * (int)sizeof(float2),
-                                          v);
-                });
-          }
-        });
-      }
-    });
+    // Blocks [BLO, BHI) of SB steps. In the slab's first chunk (FIRST) step
+    // st is the slab's row st, and its priming steps (st < n0 - 1) compute
+    // only the column levels that a window of the slab uses (column_levels).
+    auto run_blocks = [&](auto FIRST, auto BLO, auto BHI) {
+      sfor<BLO, BHI>([&](auto BLK) {
+        if (!kSkip || BLK * SB < live) {
+          sfor<0, SB>([&](auto SS) {
+            constexpr int st = BLK * SB + SS;
+            if constexpr (st + kLdsAhead < C::CR)
+              zq[st + kLdsAhead] = zcol[(st + kLdsAhead) * C::ZROW];
+            __builtin_amdgcn_sched_barrier(0);  // keep the read ahead of this step's work
+            const float2 z = zq[st];
+            const auto out = step_rsrc(row_addr, st, sp, strip_bytes);
+            row_addr += row_bytes;
+            if constexpr (N0W == 1) {
+              store_buf<C::NT_STORES>(out, lane_off, z);
+            } else {
+              column_levels<N0W, C::KT, st % C::RING, (FIRST ? st : -1)>(
+                  z, ring, lanefac, lw, w0, [&](auto J, float2 v) {
+                    store_buf<C::NT_STORES>(
+                        out, lane_off + (C::KT * J) * N1W * (int)sizeof(float2), v);
+                  });
+            }
+          });
+        }
+      });
+    };
+    // the blocks that hold priming steps run in two versions
+    constexpr int NB = C::CR / SB;
+    constexpr int PB0 = (N0W - 1 + SB - 1) / SB;
+    constexpr int PB = PB0 < NB ? PB0 : NB;
+    using B0 = std::integral_constant<int, 0>;
+    using BP = std::integral_constant<int, PB>;
+    using BN = std::integral_constant<int, NB>;
+    if (c == 0) {
+      run_blocks(std::true_type{}, B0{}, BP{});
+    } else {
+      run_blocks(std::false_type{}, B0{}, BP{});
+    }
+    run_blocks(std::false_type{}, BP{}, BN{});
     __syncthreads();
     if (c + 1 < nchunks) {
       if constexpr (!kPrefetch) load_chunk(crow + C::CR);
