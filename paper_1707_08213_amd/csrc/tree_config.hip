@@ -52,22 +52,46 @@ bool small_image(const swdft2d_plan_s* p) {
   return strips * slabs * p->batch < ncu;
 }
 
-// Split and waves per strip for small images: as many residues per stream as
-// are built (two lanes, and two waves where they exist), so that each step of
-// a wave's walk down its short slab is short; the time of a small image is
-// that of the walks (slab rows + n0 - 1 priming rows), not of the output
-// stream.
-int small_image_kg(int n0, int n1, int kg) {
-  return n0 < 64 && swdft::tree_fwd_kg_supported(n0, n1, 2) ? 2 : kg;
+// Launch of a small image. Its time is that of the longest walk of a wave
+// down its slab, and the walk costs mostly per wave: set-up, the row phase of
+// a chunk, and steps that do not pipeline with one wave per SIMD. The n0 - 1
+// priming rows at a slab top cost little, since they compute only the column
+// levels the slab's windows use. Two rules (100 x 100, measured on gfx950):
+//  - n0 <= 16: whole streams, one wave per strip and one-chunk slabs (each
+//    wave one chunk of rows: mostly priming, then its few windows), as long
+//    as the waves fit eight to a CU (16 x 16 7.0 -> 6.3 us, 8 x 8 4.4 ->
+//    4.1 us);
+//  - otherwise: streams split over two lanes and two waves where built, and
+//    the shortest slabs that keep to one workgroup per CU (32 x 32 14.5 ->
+//    12.0 us).
+struct SmallCfg {
+  bool one_chunk = false;  // first rule
+  int kg = 1, wv = 1;
+};
+
+SmallCfg small_image_cfg(const swdft2d_plan_s* p) {
+  SmallCfg c;
+  const int64_t ncu = cu_count() > 0 ? cu_count() : 256;
+  if (p->n0 <= 16) {
+    const int cr = swdft::tree_fwd_rows_per_chunk(p->n0, p->n1, 1, 1);
+    const int64_t S = std::max(1, cr - (p->n0 - 1));
+    const int64_t strips = ceil_div(p->P1, swdft::tree_fwd_columns_per_wave(p->n0, p->n1, 1));
+    if (strips * ceil_div(p->P0, S) * p->batch <= 8 * ncu) {
+      c.one_chunk = true;
+      return c;
+    }
+  }
+  c.kg = swdft::tree_fwd_default_kg(p->n0, p->n1);
+  if (p->n0 < 64 && swdft::tree_fwd_kg_supported(p->n0, p->n1, 2)) c.kg = 2;
+  c.wv = swdft::tree_fwd_wv_supported(p->n0, c.kg, 2) ? 2 : 1;
+  return c;
 }
 
 int32_t tree_kg(const swdft2d_plan_s* p) {
   if (mixed_window(p)) return 1;  // the mixed-radix kernels keep streams whole
   int kg = p->tree_kg > 0 ? p->tree_kg : env_int("SWDFT_TREE_KG", 0);
-  if (kg <= 0 || !swdft::tree_fwd_kg_supported(p->n0, p->n1, kg)) {
-    kg = swdft::tree_fwd_default_kg(p->n0, p->n1);
-    if (small_image(p)) kg = small_image_kg(p->n0, p->n1, kg);
-  }
+  if (kg <= 0 || !swdft::tree_fwd_kg_supported(p->n0, p->n1, kg))
+    kg = small_image(p) ? small_image_cfg(p).kg : swdft::tree_fwd_default_kg(p->n0, p->n1);
   return kg;
 }
 
@@ -118,7 +142,7 @@ TreeCap tree_cap(const swdft2d_plan_s* p, int kg) {
   if (c.wpc < 0) {
     c.wpc = 0;
     // small images: no cap, their many short tiles run at once
-    if (small_image(p) && !mixed_window(p) && p->n0 < 64) return c;
+    if (small_image(p) && !mixed_window(p)) return c;
     // one resident workgroup per CU for the shapes above; two for the others
     // (1024 x 1024, alternating A/B: 8 x 8 102 -> 85-92 us, 8 x 16 198 -> 193 us), and for
     // mixed-radix windows of 12 x 12 and up (12 x 12 259 -> 246 us, 24 x 24
@@ -154,7 +178,7 @@ int32_t tree_wv(const swdft2d_plan_s* p, int kg, int wpc) {
   int wv = p->tree_wv > 0 ? p->tree_wv : env_int("SWDFT_TREE_WV", 0);
   if (wv <= 0) {
     wv = (wpc == 1 && two_waves_by_default(p->n0, p->n1, kg)) ? 2 : 1;
-    if (small_image(p) && p->n0 < 64 && swdft::tree_fwd_wv_supported(p->n0, kg, 2)) wv = 2;
+    if (small_image(p)) wv = small_image_cfg(p).wv;
   }
   if (!swdft::tree_fwd_wv_supported(p->n0, kg, wv)) wv = 1;
   if (!swdft::tree_fwd_wv_supported(p->n0, kg, wv)) wv = 2;  // n0 = 64 unsplit: two waves only
@@ -169,23 +193,23 @@ int32_t tree_slab(const swdft2d_plan_s* p, int kg, int wv, const TreeCap& cap) {
   const int cr = tree_chunk_rows(p, kg, wv);
   const int64_t nstrips = ceil_div(p->P1, swdft::tree_fwd_columns_per_wave(p->n0, p->n1, kg));
   int64_t S = p->tree_slab > 0 ? p->tree_slab : env_int("SWDFT_TREE_SLAB", 0);
-  if (small_image(p) && !mixed_window(p) && p->n0 < 64) {
-    // Small images: a wave's time is its walk of S + n0 - 1 rows (the slab and
-    // the priming rows above it), and with more tiles than SIMDs the tiles
-    // queue. S minimises (S + n0 - 1 + F) * max(1, waves / SIMDs), F a
-    // per-tile cost in rows (row phase and set-up). A slab need not be a
-    // whole number of chunks (long chunks skip the steps past its end).
+  if (small_image(p) && !mixed_window(p)) {
+    // Small images (small_image_cfg): one-chunk slabs for whole streams on
+    // one wave per strip under the first rule; otherwise the shortest slabs
+    // that keep to one workgroup per CU. A slab need not be a whole number
+    // of chunks (long chunks skip the steps past its end).
     if (S <= 0) {
-      const int64_t simds = 4 * (cu_count() > 0 ? cu_count() : 256);
-      constexpr int64_t kTileRows = 8;
-      double best = 0.0;
-      for (int64_t s = 1; s <= p->P0; ++s) {
-        const int64_t waves = nstrips * ceil_div(p->P0, s) * p->batch * wv;
-        const double t = (double)(s + p->n0 - 1 + kTileRows) *
-                         std::max(1.0, (double)waves / (double)simds);
-        if (S <= 0 || t < best) {
-          S = s;
-          best = t;
+      const SmallCfg sc = small_image_cfg(p);
+      if (sc.one_chunk && kg == 1 && wv == 1) {
+        S = std::max(1, cr - (p->n0 - 1));
+      } else {
+        const int64_t ncu = cu_count() > 0 ? cu_count() : 256;
+        S = p->P0;
+        for (int64_t s = 1; s <= p->P0; ++s) {
+          if (nstrips * ceil_div(p->P0, s) * p->batch <= ncu) {
+            S = s;
+            break;
+          }
         }
       }
     }

@@ -316,10 +316,11 @@ def test_stream_validation():
 
 @pytest.mark.parametrize("n0,n1,kg,cols,wv", [
     (64, 64, 1, 1, 2), (64, 32, 2, 1, 1), (64, 16, 4, 1, 1), (64, 8, 8, 1, 2), (64, 4, 8, 2, 2),
-    (64, 1, 8, 8, 1), (32, 64, 1, 1, 1), (4, 64, 1, 1, 1)])
+    (64, 1, 8, 8, 2), (32, 64, 1, 1, 1), (4, 64, 1, 1, 1)])
 def test_window64_tree_shapes(n0, n1, kg, cols, wv):
     """n0 = 64 splits each stream over KG = min(8, 64/n1) lanes; 64 x 64, whose
-    stream stays whole, and the capped n1 <= 8 shapes run two waves per strip."""
+    stream stays whole, the capped n1 <= 8 shapes and 64 x 1 (a small image
+    here: 38 strips) run two waves per strip."""
     st, h = make_plan(200, 300, n0, n1)
     assert st == 0
     buf = ctypes.create_string_buffer(512)
@@ -349,17 +350,18 @@ def test_window64_limits_of_other_paths():
 
 
 @pytest.mark.parametrize("N,n,slab,slabs", [
-    (100, 16, 8, 11),     # 43 two-lane strips x 11 slabs of 8 rows: 946 waves
-    (100, 32, 10, 7),     # 69 strips x 7 slabs of 10 rows (not whole 128-row chunks)
-    (100, 8, 5, 19),      # 24 strips x 19 slabs of 5 rows
-    (100, 64, 128, 1),    # n0 = 64 keeps whole columns (one 128-row chunk)
+    (100, 16, 1, 85),     # one-chunk slabs: 22 strips x 85 slabs of 1 row, 1870 waves
+    (100, 8, 1, 93),      # 12 strips x 93 slabs of 1 row
+    (100, 32, 23, 3),     # 69 two-lane strips x 3 slabs: 207 workgroups (not whole chunks)
+    (100, 64, 7, 6),      # 37 strips x 6 slabs of 7 rows: 222 workgroups
     (1024, 16, 1024, 1),  # one workgroup per CU walking whole columns
 ])
 def test_tree_slab_rule(N, n, slab, slabs):
     """Small images (fewer tiles than compute units with one-chunk slabs;
-    256 assumed without a device) take two-lane streams on two waves and the
-    slab S that minimises (S + n0 - 1 + 8) * max(1, waves / SIMDs); larger
-    images keep their whole-column or about-4096-tile rules."""
+    256 assumed without a device): for n0 <= 16 one chunk of rows per wave
+    while the waves fit eight to a CU; otherwise the shortest slabs that keep
+    to one workgroup per CU. Larger images keep their whole-column or
+    about-4096-tile rules."""
     st, h = make_plan(N, N, n, n)
     assert st == 0
     buf = ctypes.create_string_buffer(512)
@@ -402,14 +404,14 @@ def test_mixed_radix_plan_rules():
         S["SWDFT_E_NOT_POW2"]
 
 
-@pytest.mark.parametrize("N,n,kg,wv", [(100, 32, 2, 2), (100, 8, 2, 2), (100, 16, 2, 2),
+@pytest.mark.parametrize("N,n,kg,wv", [(100, 32, 2, 2), (100, 8, 1, 1), (100, 16, 1, 1),
                                        (100, 4, 1, 1), (100, 64, 1, 2),
                                        (1024, 32, 1, 2), (1024, 8, 2, 1)])
 def test_tree_small_image_split(N, n, kg, wv):
-    """Small images (fewer tiles than compute units) split their streams over
-    two lanes and two waves where those kernels exist (n0 = 8 to 32), so each
-    step of a short walk is short; large images keep the large-image
-    defaults."""
+    """Small images (fewer tiles than compute units) keep whole streams on one
+    wave per strip for n0 <= 16 (one-chunk slabs), and split their streams
+    over two lanes and two waves where those kernels exist for n0 = 32; large
+    images keep the large-image defaults."""
     st, h = make_plan(N, N, n, n)
     assert st == 0
     buf = ctypes.create_string_buffer(512)
