@@ -523,8 +523,12 @@ __device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float
   __syncthreads();
   for (int c = 0; c < nchunks; ++c) {
     const int64_t crow = row0 + (int64_t)c * C::CR;
-    // past the last chunk this reads zeros and touches no memory
-    if constexpr (kPrefetch) load_chunk(crow + C::CR);
+    // (the loads of a chunk past the image bottom read zeros and touch no
+    // memory; none is issued after the slab's last chunk, whose wave would
+    // otherwise wait for them before it ends)
+    if constexpr (kPrefetch) {
+      if (c + 1 < nchunks) load_chunk(crow + C::CR);
+    }
     __builtin_amdgcn_sched_barrier(0);
 
     // ---- column phase: CR steps down the slab, one input row each. The Z
