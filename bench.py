@@ -13,9 +13,12 @@ count, the normwise relative error on sampled windows, and the FP64 oracle
 timed on the host cores on a bounded sample of the same windows.
 
 Other workloads (one JSON line each, same fields where they apply):
-  cplx2048 - 2048 x 512 complex64, 32 x 8 windows (tree; dense MFMA variant).
+  cplx2048 - 2048 x 512 complex64, 32 x 8 windows (tree; dense MFMA variant;
+             adjoint).
   grad256  - 16 x 256 x 256 real FP32, 16 x 16 windows, forward + adjoint of
              L = sum w |A|^2 (band mask w); the adjoint kernel is read-bound.
+  The adjoint legs also time a read-only probe over dy (the read ceiling at
+  the same byte count).
   uneven64 - 64 real FP32 images of uneven sizes and window shapes in one
              batched graph launch, after autotuning.
   mixed1024 - 1024 x 1024 real FP32, 12 x 12 windows through the mixed-radix
@@ -430,7 +433,9 @@ def run_cplx2048(args, swd, dev) -> dict:
                                 "tree_adj_kernel<32,8,complex> + reduce",
                                 med_ms=statistics.median(a_durs)),
            "avg_launch_us": a_ms * 1e3}
-    log(f"adjoint: {a_ms * 1e3:.1f} us/launch ({adj['roofline']['achieved']:.0f} GB/s)")
+    adj["read_probe"] = read_probe_leg(swd, y, stream)
+    log(f"adjoint: {a_ms * 1e3:.1f} us/launch ({adj['roofline']['achieved']:.0f} GB/s); "
+        f"read probe over dy {adj['read_probe']['GB/s']:.0f} GB/s")
     pr, pc = workloads.pixel_sample(N0, N1, 256, 57)
     dx_s = dx[0].cpu().numpy()[pr, pc]
     dy_np = y[0].cpu().numpy() if not args.no_cpu_baseline else None
@@ -700,7 +705,9 @@ def run_grad256(args, swd, dev) -> dict:
                     med_ms=f_med)
     rf_b = roofline(plan.output_bytes() + x.numel() * 4, b_ms,
                     "tree_adj_kernel<16,16,real> + reduce")
-    log(f"fwd {f_ms * 1e3:.1f} us, bwd {b_ms * 1e3:.1f} us ({rf_b['achieved']:.0f} GB/s)")
+    rprobe = read_probe_leg(swd, dy, stream)
+    log(f"fwd {f_ms * 1e3:.1f} us, bwd {b_ms * 1e3:.1f} us ({rf_b['achieved']:.0f} GB/s); "
+        f"read probe over dy {rprobe['GB/s']:.0f} GB/s")
     r, c = workloads.pixel_sample(N0, N1, 256, 55)
     err = None
     cpu = None
@@ -725,8 +732,22 @@ def run_grad256(args, swd, dev) -> dict:
         "N0": N0, "N1": N1, "n0": n0, "n1": n1, "batch": B, "algo": "tree",
         "coeffs_per_step": coeffs})
     out.update({"forward_ms": f_step * 1e3, "backward_ms": b_step * 1e3, "roofline": rf_b,
-                "roofline_forward": rf_f, "rel_err": err, "cpu_baseline": cpu})
+                "roofline_forward": rf_f, "read_probe": rprobe, "rel_err": err,
+                "cpu_baseline": cpu})
     return out
+
+
+def read_probe_leg(swd, buf, stream) -> dict:
+    """Time the library's read probe over buf (the adjoint's dy): the
+    empirical HBM read ceiling at that byte count."""
+    import torch
+    sink = torch.zeros(1, dtype=torch.float32, device=buf.device)
+    swd.read_probe(buf, sink)
+    torch.cuda.synchronize()
+    ms, _, _ = time_launches(lambda: swd.read_probe(buf, sink), 10, stream)
+    nbytes = buf.numel() * buf.element_size()
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"GB/s": gbs, "frac": gbs / PEAK_HBM_GBS, "bytes": nbytes}
 
 
 def run_uneven64(args, swd, dev) -> dict:

@@ -276,6 +276,16 @@ swdft_status_t swdft2d_twiddles(swdft2d_plan_t plan, int32_t axis, float* out, i
  * given byte count. */
 swdft_status_t swdft2d_write_probe(void* y, int64_t bytes, hipStream_t stream);
 
+/* Measurement aid (not part of the transform): read `bytes` bytes at x
+ * (16-byte aligned, bytes a multiple of 8) with non-temporal 16-byte loads
+ * (16384 workgroups of 256 lanes sweeping the buffer front to back). Nothing
+ * is written in practice: *sink (device memory, 4-byte aligned) is stored to
+ * only if the sum of the values read is one particular NaN bit pattern.
+ * Timing it gives the empirical HBM read ceiling at a given byte count, the
+ * bound of swdft2d_backward's input stream. Checks: x, sink non-null and
+ * bytes > 0, a multiple of 8 (E_ARG); alignment (E_ALIGN). */
+swdft_status_t swdft2d_read_probe(const void* x, int64_t bytes, float* sink, hipStream_t stream);
+
 /* ---- Streaming 2D sliding-window DFT: the order of Sec. 4.3 in which the
  * loops over trees are innermost, for rows that arrive one after another
  * (a real-time task). The column-level state of the trees (m0 n0 / 2 complex

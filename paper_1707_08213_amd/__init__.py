@@ -21,7 +21,7 @@ from . import _lib
 from ._lib import SwdftError, check, lib
 
 __all__ = ["Plan", "BatchedPlan", "Plan3D", "Stream2D", "swdft2d", "swdft2d_batched",
-           "swdft2d_backward", "swdft3d", "SWDFT2dFn", "write_probe", "SwdftError", "output_shape"]
+           "swdft2d_backward", "swdft3d", "SWDFT2dFn", "write_probe", "read_probe", "SwdftError", "output_shape"]
 
 _DTYPES = {
     torch.float32: _lib.SWDFT_R32, torch.complex64: _lib.SWDFT_C32,
@@ -506,6 +506,20 @@ class SWDFT2dFn(torch.autograd.Function):
         N0, N1 = shape[-2], shape[-1]
         dx = swdft2d_backward(gy.contiguous(), N0, N1, dtype=dtype, norm=norm)
         return dx.reshape(shape), None, None, None
+
+
+def read_probe(buf: torch.Tensor, sink: torch.Tensor | None = None) -> None:
+    """Read buf with non-temporal 16-byte loads (HBM read-ceiling probe); sink
+    is a device float32 tensor that is written only if the values read sum to
+    one particular NaN."""
+    if not buf.is_cuda or not buf.is_contiguous():
+        raise ValueError("probe buffer must be a contiguous cuda tensor")
+    if sink is None:
+        sink = torch.empty(1, dtype=torch.float32, device=buf.device)
+    with torch.cuda.device(buf.device):
+        stream = torch.cuda.current_stream(buf.device).cuda_stream
+        check(lib.swdft2d_read_probe(buf.data_ptr(), buf.numel() * buf.element_size(),
+                                     sink.data_ptr(), stream), "swdft2d_read_probe")
 
 
 def write_probe(buf: torch.Tensor, nbytes: int | None = None) -> None:

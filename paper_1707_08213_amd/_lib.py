@@ -47,6 +47,7 @@ SIGNATURES = {
     "swdft2d_status_string": (ctypes.c_char_p, [_int]),
     "swdft2d_last_error": (ctypes.c_char_p, []),
     "swdft2d_write_probe": (_int, [_vp, _i64, _vp]),
+    "swdft2d_read_probe": (_int, [_vp, _i64, _vp, _vp]),
     "swdft2d_twiddles": (_int, [_vp, _i32, ctypes.POINTER(ctypes.c_float), _i32]),
     "swdft2d_plan_batched": (_int, [_PLAN_P, _vp, _i64, _int]),
     "swdft2d_tune": (_int, [_vp, _vp, _vp, _vp]),

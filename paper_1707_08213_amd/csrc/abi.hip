@@ -135,12 +135,16 @@ int32_t adj_slab(const swdft2d_plan_s* p, int kg) {
   const char* env = std::getenv("SWDFT_ADJ_SLAB");
   if (env) S = std::atoll(env);
   if (S <= 0) {
+    // Whole columns once they give about 1.5 waves per CU; otherwise about
+    // two per CU (512 waves): more, shorter slabs re-read more priming rows of
+    // dy than their extra waves gain (2048x512 / 32x8: 4 slabs 381 us, 8 slabs
+    // 392 us; 1024^2 / 16x16: 2 slabs 372 us, 4 slabs 375 us).
     const int64_t waves_full = nstrips * p->batch;
-    if (waves_full >= 768) {
+    if (waves_full >= 384) {
       S = full;
     } else {
-      S = ceil_div(p->N0 * waves_full, 1024);
-      S = std::max<int64_t>(S, 8 * (int64_t)(p->n0 - 1));
+      const int64_t slabs = std::max<int64_t>(1, (512 + waves_full / 2) / waves_full);
+      S = std::max<int64_t>(ceil_div(p->N0, slabs), 8 * (int64_t)(p->n0 - 1));
     }
   }
   S = std::max<int64_t>(S, cr);
@@ -597,6 +601,16 @@ const char* swdft2d_status_string(swdft_status_t s) {
 }
 
 const char* swdft2d_last_error(void) { return g_last_error.c_str(); }
+
+swdft_status_t swdft2d_read_probe(const void* x, int64_t bytes, float* sink, hipStream_t stream) {
+  if (!x || !sink) return fail(SWDFT_E_ARG, "probe buffer or sink is null");
+  if (bytes <= 0 || bytes % 8) return fail(SWDFT_E_ARG, "probe size must be a positive multiple of 8");
+  if ((uintptr_t)x % 16) return fail(SWDFT_E_ALIGN, "probe buffer is not 16-byte aligned");
+  if ((uintptr_t)sink % 4) return fail(SWDFT_E_ALIGN, "probe sink is not 4-byte aligned");
+  hipError_t e = swdft::launch_read_probe(x, bytes, sink, stream);
+  if (e != hipSuccess) return device_fail(e, "probe launch");
+  return SWDFT_OK;
+}
 
 swdft_status_t swdft2d_write_probe(void* y, int64_t bytes, hipStream_t stream) {
   if (!y) return fail(SWDFT_E_ARG, "probe buffer is null");

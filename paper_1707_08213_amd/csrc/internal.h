@@ -198,5 +198,6 @@ hipError_t launch_swfft(int n0, int n1, bool real_input, const void* x, float2* 
 int swfft_windows_per_group(int n0, int n1);
 
 hipError_t launch_write_probe(float2* y, int64_t n_float2, hipStream_t stream);
+hipError_t launch_read_probe(const void* x, int64_t bytes, float* sink, hipStream_t stream);
 
 }  // namespace swdft

@@ -49,6 +49,7 @@ using tree::kOutOfRange;
 using tree::load_buf;
 using tree::sfor;
 using tree::store_buf;
+using tree::store_buf4;
 using tree::uload;
 using tree::uniform_copy;
 using tree::xcd_tile;
@@ -107,15 +108,19 @@ __device__ __forceinline__ void butterfly(const float2 (&a)[3], const float2* w,
     out(std::integral_constant<int, 0>{}, cadd(a[0], a[1]));
     out(std::integral_constant<int, 1>{}, csub(a[0], a[1]));
   } else {
-    // sqrt(3)/2 = -Im Omega[N/3], from the FP64-generated table
+    // sqrt(3)/2 = -Im Omega[N/3], from the FP64-generated table. Every
+    // rounding is written out (fused multiply-adds): X1,2 = t2 -/+ i c3 d
+    // with t2 = a0 - t1 / 2.
     const float c3 = -uload(w + N / 3).y;
     const float2 t1 = cadd(a[1], a[2]);
-    const float2 t2 = make_float2(a[0].x - 0.5f * t1.x, a[0].y - 0.5f * t1.y);
+    const float2 t2 = make_float2(__builtin_fmaf(-0.5f, t1.x, a[0].x),
+                                  __builtin_fmaf(-0.5f, t1.y, a[0].y));
     const float2 d = csub(a[1], a[2]);
-    const float2 t3 = make_float2(c3 * d.y, -c3 * d.x);  // -i (sqrt(3)/2) d
     out(std::integral_constant<int, 0>{}, cadd(a[0], t1));
-    out(std::integral_constant<int, 1>{}, cadd(t2, t3));
-    out(std::integral_constant<int, 2>{}, csub(t2, t3));
+    out(std::integral_constant<int, 1>{}, make_float2(__builtin_fmaf(c3, d.y, t2.x),
+                                                      __builtin_fmaf(-c3, d.x, t2.y)));
+    out(std::integral_constant<int, 2>{}, make_float2(__builtin_fmaf(-c3, d.y, t2.x),
+                                                      __builtin_fmaf(c3, d.x, t2.y)));
   }
 }
 
@@ -218,8 +223,25 @@ struct MixedCfg {
   static constexpr int PPW = CR / R;                        // row passes per chunk
   static constexpr int ZS = N1W + 1;
   static constexpr int ZROW = QW * ZS;
-  static constexpr int LDS_FLOAT2 = CR * ZROW;
-  static constexpr bool NT_STORES = N1W == 16;
+  static constexpr int WE = N0W * N1W;                     // values per window
+  // Output of one step: the QW windows of the strip at one window row, a
+  // contiguous block of QW * WE values. Where a window row of n1 values is
+  // not a whole number of 128-byte lines (n1 != 16) the lanes' values go
+  // through LDS and leave in contiguous 16- or 8-byte pieces per lane: the
+  // direct stores cover 8 n1 bytes of each of QW windows per instruction,
+  // pieces of lines that queue in L2 (n1 = 9, 12, 24 waited on their stores
+  // 33-67% of their cycles).
+  static constexpr bool STAGE = N1W != 16;
+  static constexpr int SE = STAGE ? QW * WE : 1;            // staged values per step
+  static constexpr bool VEC4 = WE % 2 == 0;                 // blocks start 16-byte aligned
+  static constexpr int PIECE = VEC4 ? 16 : 8;               // bytes per lane and store
+  static constexpr int NPIECE = SE * 8 / PIECE;
+  static constexpr int NR = (NPIECE + 63) / 64;             // stores per lane and step
+  static constexpr int OB_OFF = (CR * ZROW + 1) / 2 * 2;   // 16-byte aligned
+  static constexpr int LDS_FLOAT2 = OB_OFF + SE;
+  // Non-temporal stores where they cover whole lines: rows of 16 values
+  // (direct), or staged blocks whose windows start on line boundaries.
+  static constexpr bool NT_STORES = STAGE ? (WE * 8) % 128 == 0 : N1W == 16;
   static_assert((int64_t)CR * SWDFT_MAX_ROW * 8 <= (int64_t)kOutOfRange,
                 "one chunk of input rows must stay addressable with 32-bit offsets");
 };
@@ -229,7 +251,8 @@ __global__ __launch_bounds__(64) void tree_mixed_kernel(const void* __restrict__
                                                         float2* __restrict__ y, TreeGeom g_in,
                                                         TwiddlesF32 tw) {
   using C = MixedCfg<N0W, N1W, REAL>;
-  __shared__ float2 zl[C::LDS_FLOAT2];
+  __shared__ __align__(16) float2 zl[C::LDS_FLOAT2];
+  float2* const ob = zl + C::OB_OFF;  // staged output of one step
   const TreeGeom g = uniform_copy(g_in);
   int id = g.order ? (int)blockIdx.x : xcd_tile(blockIdx.x, gridDim.x);
   const int strip = id % g.nstrips;
@@ -288,6 +311,7 @@ __global__ __launch_bounds__(64) void tree_mixed_kernel(const void* __restrict__
       (uint32_t)(min((int64_t)C::QW, g.P1 - q1_0) * (N0W * N1W * (int)sizeof(float2))));
   const uint32_t lane_off =
       cp_live ? (uint32_t)((cp_c * (N0W * N1W) + cp_k1) * (int)sizeof(float2)) : kOutOfRange;
+  float2* const ob_lane = ob + cp_c * C::WE + cp_k1;
 
   float2 ring[Radix<N0W>::RING_TOTAL];
   sfor<0, Radix<N0W>::RING_TOTAL>([&](auto K) { ring[K] = make_float2(0.f, 0.f); });
@@ -335,7 +359,31 @@ __global__ __launch_bounds__(64) void tree_mixed_kernel(const void* __restrict__
         const float2 z = zcol[row * C::ZROW];
         const auto out = tree::step_rsrc(row_addr, row, sp, strip_bytes);
         row_addr += row_bytes;
-        if constexpr (N0W == 1) {
+        if constexpr (C::STAGE) {
+          // value (c, k0, k1) to ob[c WE + k0 n1 + k1], then the block in
+          // contiguous pieces (the LDS operations of a wave run in order)
+          if constexpr (N0W == 1) {
+            if (cp_live) ob_lane[0] = z;
+          } else {
+            column_levels<N0W, st>(z, ring, w0, [&](auto K, float2 v) {
+              if (cp_live) ob_lane[K * N1W] = v;
+            });
+          }
+          __builtin_amdgcn_wave_barrier();
+          sfor<0, C::NR>([&](auto RR) {
+            constexpr int rr = RR;
+            const int piece = lane + 64 * rr;
+            if (rr + 1 < C::NR || piece < C::NPIECE) {
+              if constexpr (C::VEC4) {
+                const float4 v = reinterpret_cast<const float4*>(ob)[piece];
+                store_buf4<C::NT_STORES>(out, (uint32_t)(piece * 16), v);
+              } else {
+                store_buf<C::NT_STORES>(out, (uint32_t)(piece * 8), ob[piece]);
+              }
+            }
+          });
+          __builtin_amdgcn_wave_barrier();
+        } else if constexpr (N0W == 1) {
           store_buf<C::NT_STORES>(out, lane_off, z);
         } else {
           column_levels<N0W, st>(z, ring, w0, [&](auto K, float2 v) {

@@ -1,5 +1,6 @@
-// Measurement aid: fill a buffer with a constant at the device's HBM write
-// ceiling, for comparison with the tree's output stream.
+// Measurement aids: fill a buffer with a constant at the device's HBM write
+// ceiling, for comparison with the tree's output stream, and read a buffer at
+// the HBM read ceiling, for comparison with the adjoint's input stream.
 #include <cstdint>
 
 #include "internal.h"
@@ -29,7 +30,48 @@ __global__ __launch_bounds__(kProbeThreads) void write_probe_kernel(float2* __re
   if (first && head + 2 * n4 < n) y[n - 1] = v;
 }
 
+// Read: 16384 workgroups of 256 lanes (the fastest of 1024-16384 measured
+// on gfx950), each lane four non-temporal 16-byte loads per step of a
+// grid-stride sweep; an 8-byte tail element is read by lane 0. The loaded
+// values are summed and stored only if the sum is one particular NaN, which
+// keeps the loads without writing anything in practice.
+constexpr int kReadBlocks = 16384;
+constexpr int kReadThreads = 256;
+constexpr int kReadUnroll = 4;
+
+__global__ __launch_bounds__(kReadThreads) void read_probe_kernel(const float4* __restrict__ x,
+                                                                  int64_t n4, bool tail,
+                                                                  float* __restrict__ sink) {
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  const f4v* xv = reinterpret_cast<const f4v*>(x);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float acc = 0.f;
+  for (; i + (kReadUnroll - 1) * stride < n4; i += kReadUnroll * stride) {
+    f4v v[kReadUnroll];
+#pragma unroll
+    for (int u = 0; u < kReadUnroll; ++u) v[u] = __builtin_nontemporal_load(xv + i + u * stride);
+#pragma unroll
+    for (int u = 0; u < kReadUnroll; ++u) acc += (v[u].x + v[u].y) + (v[u].z + v[u].w);
+  }
+  for (; i < n4; i += stride) {
+    const f4v v = xv[i];
+    acc += (v.x + v.y) + (v.z + v.w);
+  }
+  if (tail && blockIdx.x == 0 && threadIdx.x == 0) {
+    const float2 t = reinterpret_cast<const float2*>(x + n4)[0];
+    acc += t.x + t.y;
+  }
+  if (__float_as_uint(acc) == 0x7fc0b00fu) sink[0] = acc;
+}
+
 }  // namespace
+
+hipError_t launch_read_probe(const void* x, int64_t bytes, float* sink, hipStream_t stream) {
+  hipLaunchKernelGGL(read_probe_kernel, dim3(kReadBlocks), dim3(kReadThreads), 0, stream,
+                     static_cast<const float4*>(x), bytes / 16, bytes % 16 != 0, sink);
+  return hipGetLastError();
+}
 
 hipError_t launch_write_probe(float2* y, int64_t n_float2, hipStream_t stream) {
   hipLaunchKernelGGL(write_probe_kernel, dim3(kProbeBlocks), dim3(kProbeThreads), 0, stream, y,

@@ -164,6 +164,15 @@ def test_describe_and_status_strings():
     assert lib.swdft2d_status_string(99) == b"SWDFT_E_UNKNOWN"
 
 
+def test_read_probe_checks():
+    assert lib.swdft2d_read_probe(None, 64, 0x20000, None) == S["SWDFT_E_ARG"]
+    assert lib.swdft2d_read_probe(0x10000, 64, None, None) == S["SWDFT_E_ARG"]
+    assert lib.swdft2d_read_probe(0x10000, 12, 0x20000, None) == S["SWDFT_E_ARG"]
+    assert lib.swdft2d_read_probe(0x10000, 0, 0x20000, None) == S["SWDFT_E_ARG"]
+    assert lib.swdft2d_read_probe(0x10008, 64, 0x20000, None) == S["SWDFT_E_ALIGN"]
+    assert lib.swdft2d_read_probe(0x10000, 64, 0x20002, None) == S["SWDFT_E_ALIGN"]
+
+
 def test_write_probe_checks():
     assert lib.swdft2d_write_probe(None, 64, None) == S["SWDFT_E_ARG"]
     assert lib.swdft2d_write_probe(0x10000, 12, None) == S["SWDFT_E_ARG"]

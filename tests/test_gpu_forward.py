@@ -334,3 +334,18 @@ def test_tree_fig4_size_short_slabs(swd, orc, n):
         assert rel_err(y[b], orc.swdft2d(x[b].astype(np.float64), n, n)) <= TOL_F32
     yc = gpu_full(swd, xc, n, n)
     assert rel_err(yc, orc.swdft2d(xc.astype(np.complex128), n, n)) <= TOL_F32
+
+
+@pytest.mark.parametrize("count", [1 << 20, (1 << 20) + 1, 3, 1], ids=["large", "tail", "short", "one"])
+def test_read_probe_reads_only(swd, count):
+    """The read probe leaves its buffer and, for ordinary data, its sink
+    untouched (an 8-byte tail included)."""
+    buf = torch.randn(count, dtype=torch.complex64, device="cuda")
+    before = buf.clone()
+    sink = torch.full((1,), 42.0, dtype=torch.float32, device="cuda")
+    from paper_1707_08213_amd import _lib
+    _lib.check(_lib.lib.swdft2d_read_probe(buf.data_ptr(), 8 * count, sink.data_ptr(), None),
+               "swdft2d_read_probe")
+    torch.cuda.synchronize()
+    assert torch.equal(buf, before)
+    assert float(sink[0]) == 42.0
