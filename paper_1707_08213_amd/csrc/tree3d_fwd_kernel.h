@@ -188,22 +188,33 @@ __device__ __forceinline__ void tree3_fwd_tile(const void* __restrict__ xv, floa
   const float2* zcol = zl + (cp_c * N1W + cp_k1) * C::ZS + cp_k2;
   for (int c = 0; c < nchunks; ++c) {
     const int64_t crow = row0 + (int64_t)c * C::CR;
-    load_chunk(crow + C::CR);
+    if (c + 1 < nchunks) load_chunk(crow + C::CR);
     __builtin_amdgcn_sched_barrier(0);
 
     // step st writes window row q0 = crow + st - (n0 - 1) if it lies in the slab
     const tree::StepSpan sp = tree::step_span(crow, row0, q0_end, N0W - 1, C::CR);
     uint64_t row_addr = tree::uniform_u64((uint64_t)(uintptr_t)ystrip +
                                           (uint64_t)(crow - (N0W - 1)) * row_bytes);
-    sfor<0, C::CR>([&](auto STc) {
-      constexpr int st = STc;
-      const float2 z = zcol[st * C::ZROW];
-      const auto out = tree::step_rsrc(row_addr, st, sp, strip_bytes);
-      row_addr += row_bytes;
-      column_levels<N0W, 1, st % C::RING>(z, ring, lanefac, lw, tw.w0, [&](auto J, float2 v) {
-        store_buf<C::NT_STORES>(out, lane_off + J * C::NK * (int)sizeof(float2), v);
+    // In the slab's first chunk step st is the slab's row st: its priming
+    // steps (st < n0 - 1) compute only the axis-0 levels the slab's windows
+    // use (column_levels, as in the 2D kernel).
+    auto run_steps = [&](auto FIRST) {
+      sfor<0, C::CR>([&](auto STc) {
+        constexpr int st = STc;
+        const float2 z = zcol[st * C::ZROW];
+        const auto out = tree::step_rsrc(row_addr, st, sp, strip_bytes);
+        row_addr += row_bytes;
+        column_levels<N0W, 1, st % C::RING, (FIRST ? st : -1)>(
+            z, ring, lanefac, lw, tw.w0, [&](auto J, float2 v) {
+              store_buf<C::NT_STORES>(out, lane_off + J * C::NK * (int)sizeof(float2), v);
+            });
       });
-    });
+    };
+    if (c == 0) {
+      run_steps(std::true_type{});
+    } else {
+      run_steps(std::false_type{});
+    }
     __syncthreads();
     if (c + 1 < nchunks) {
       plane_phase();

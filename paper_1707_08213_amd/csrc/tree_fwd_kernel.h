@@ -307,21 +307,6 @@ __device__ __forceinline__ void store_buf(__amdgpu_buffer_rsrc_t r, uint32_t off
   __builtin_amdgcn_raw_buffer_store_b64(t, r, (int)off, 0, NT ? kNonTemporal : 0);
 }
 
-typedef unsigned u4v __attribute__((ext_vector_type(4)));
-
-// 16-byte store at byte offset off of a buffer resource, non-temporal by
-// default.
-template <bool NT = true>
-__device__ __forceinline__ void store_buf4(__amdgpu_buffer_rsrc_t r, uint32_t off, float4 v) {
-  constexpr int kNonTemporal = 2;
-  u4v t;
-  t.x = __float_as_uint(v.x);
-  t.y = __float_as_uint(v.y);
-  t.z = __float_as_uint(v.z);
-  t.w = __float_as_uint(v.w);
-  __builtin_amdgcn_raw_buffer_store_b128(t, r, (int)off, 0, NT ? kNonTemporal : 0);
-}
-
 __device__ __forceinline__ void store_buf_nt(__amdgpu_buffer_rsrc_t r, uint32_t off, float2 v) {
   store_buf<true>(r, off, v);
 }

@@ -49,7 +49,6 @@ using tree::kOutOfRange;
 using tree::load_buf;
 using tree::sfor;
 using tree::store_buf;
-using tree::store_buf4;
 using tree::uload;
 using tree::uniform_copy;
 using tree::xcd_tile;
@@ -153,7 +152,13 @@ __device__ __forceinline__ void row_levels(float2 (&v)[N1W], const float2* w1) {
 
 // Column levels for one new row (step ST of a chunk that starts at a multiple
 // of the ring period): z is level 0 of the new position. emit(k0, value).
-template <int N0W, int ST, typename Emit>
+// T0 >= 0 marks the row as the T0-th of a slab whose first window starts at
+// the slab's first row: level u of the row feeds only the windows ending at
+// rows p .. p + s_u - 1, so below T0 = n0 - 1 it is computed only when
+// T0 >= n0 - s_u, and level u-1 is kept in the ring only when
+// T0 >= n0 - s_{u-1} (its last reader, level u at p + (r_u - 1) s_u, is then
+// used). T0 = -1 computes every level.
+template <int N0W, int ST, int T0 = -1, typename Emit>
 __device__ __forceinline__ void column_levels(float2 z, float2 (&ring)[Radix<N0W>::RING_TOTAL],
                                               const float2* w0, Emit&& emit) {
   using RX = Radix<N0W>;
@@ -166,6 +171,13 @@ __device__ __forceinline__ void column_levels(float2 z, float2 (&ring)[Radix<N0W
     constexpr int lp = RX::L(u - 1);
     constexpr int len = RX::ring_len(u);
     constexpr int off = RX::ring_off(u);
+    constexpr bool level_in = T0 < 0 || T0 >= N0W - RX::s(u - 1);  // level u-1 used
+    constexpr bool level_out = T0 < 0 || T0 >= N0W - s;            // level u used
+    if constexpr (!level_in) {
+      // nothing of this level or above is used at this row
+    } else if constexpr (!level_out) {
+      sfor<0, lp>([&](auto I) { ring[off + (ST % len) * lp + I] = cur[I]; });
+    } else {
     float2 nxt[N0W];
     sfor<0, lp>([&](auto I) {
       constexpr int i = I;
@@ -189,6 +201,7 @@ __device__ __forceinline__ void column_levels(float2 z, float2 (&ring)[Radix<N0W
     sfor<0, lp>([&](auto I) { ring[off + (ST % len) * lp + I] = cur[I]; });
     if constexpr (u < RX::M) {
       sfor<0, lp * r>([&](auto K) { cur[K] = nxt[K]; });
+    }
     }
   });
 }
@@ -223,25 +236,8 @@ struct MixedCfg {
   static constexpr int PPW = CR / R;                        // row passes per chunk
   static constexpr int ZS = N1W + 1;
   static constexpr int ZROW = QW * ZS;
-  static constexpr int WE = N0W * N1W;                     // values per window
-  // Output of one step: the QW windows of the strip at one window row, a
-  // contiguous block of QW * WE values. Where a window row of n1 values is
-  // not a whole number of 128-byte lines (n1 != 16) the lanes' values go
-  // through LDS and leave in contiguous 16- or 8-byte pieces per lane: the
-  // direct stores cover 8 n1 bytes of each of QW windows per instruction,
-  // pieces of lines that queue in L2 (n1 = 9, 12, 24 waited on their stores
-  // 33-67% of their cycles).
-  static constexpr bool STAGE = N1W != 16;
-  static constexpr int SE = STAGE ? QW * WE : 1;            // staged values per step
-  static constexpr bool VEC4 = WE % 2 == 0;                 // blocks start 16-byte aligned
-  static constexpr int PIECE = VEC4 ? 16 : 8;               // bytes per lane and store
-  static constexpr int NPIECE = SE * 8 / PIECE;
-  static constexpr int NR = (NPIECE + 63) / 64;             // stores per lane and step
-  static constexpr int OB_OFF = (CR * ZROW + 1) / 2 * 2;   // 16-byte aligned
-  static constexpr int LDS_FLOAT2 = OB_OFF + SE;
-  // Non-temporal stores where they cover whole lines: rows of 16 values
-  // (direct), or staged blocks whose windows start on line boundaries.
-  static constexpr bool NT_STORES = STAGE ? (WE * 8) % 128 == 0 : N1W == 16;
+  static constexpr int LDS_FLOAT2 = CR * ZROW;
+  static constexpr bool NT_STORES = N1W == 16;
   static_assert((int64_t)CR * SWDFT_MAX_ROW * 8 <= (int64_t)kOutOfRange,
                 "one chunk of input rows must stay addressable with 32-bit offsets");
 };
@@ -251,8 +247,7 @@ __global__ __launch_bounds__(64) void tree_mixed_kernel(const void* __restrict__
                                                         float2* __restrict__ y, TreeGeom g_in,
                                                         TwiddlesF32 tw) {
   using C = MixedCfg<N0W, N1W, REAL>;
-  __shared__ __align__(16) float2 zl[C::LDS_FLOAT2];
-  float2* const ob = zl + C::OB_OFF;  // staged output of one step
+  __shared__ float2 zl[C::LDS_FLOAT2];
   const TreeGeom g = uniform_copy(g_in);
   int id = g.order ? (int)blockIdx.x : xcd_tile(blockIdx.x, gridDim.x);
   const int strip = id % g.nstrips;
@@ -311,7 +306,6 @@ __global__ __launch_bounds__(64) void tree_mixed_kernel(const void* __restrict__
       (uint32_t)(min((int64_t)C::QW, g.P1 - q1_0) * (N0W * N1W * (int)sizeof(float2))));
   const uint32_t lane_off =
       cp_live ? (uint32_t)((cp_c * (N0W * N1W) + cp_k1) * (int)sizeof(float2)) : kOutOfRange;
-  float2* const ob_lane = ob + cp_c * C::WE + cp_k1;
 
   float2 ring[Radix<N0W>::RING_TOTAL];
   sfor<0, Radix<N0W>::RING_TOTAL>([&](auto K) { ring[K] = make_float2(0.f, 0.f); });
@@ -343,7 +337,7 @@ __global__ __launch_bounds__(64) void tree_mixed_kernel(const void* __restrict__
   __syncthreads();
   for (int c = 0; c < nchunks; ++c) {
     const int64_t crow = row0 + (int64_t)c * C::CR;
-    load_chunk(crow + C::CR);  // past the last chunk: zeros, no memory touched
+    if (c + 1 < nchunks) load_chunk(crow + C::CR);
     __builtin_amdgcn_sched_barrier(0);
     // one ring period unrolled (its slots are fixed registers), repeated
     const float2* zcol = zl + cp_c * C::ZS + cp_k1;
@@ -351,47 +345,40 @@ __global__ __launch_bounds__(64) void tree_mixed_kernel(const void* __restrict__
     const tree::StepSpan sp = tree::step_span(crow, row0, q0_end, N0W - 1, C::CR);
     uint64_t row_addr = tree::uniform_u64((uint64_t)(uintptr_t)ystrip +
                                           (uint64_t)(crow - (N0W - 1)) * row_bytes);
-#pragma clang loop unroll(disable)
-    for (int sc = 0; sc < C::CR / C::PERIOD; ++sc) {
+    // step `row` of period sc; T0 >= 0 (the slab's first chunk, whose row
+    // `row` is the slab's row `row`) lets the priming steps skip the levels
+    // no window of the slab uses
+    auto period = [&](int sc, auto T0BASE) {
       sfor<0, C::PERIOD>([&](auto STc) {
         constexpr int st = STc;
         const int row = sc * C::PERIOD + st;
         const float2 z = zcol[row * C::ZROW];
         const auto out = tree::step_rsrc(row_addr, row, sp, strip_bytes);
         row_addr += row_bytes;
-        if constexpr (C::STAGE) {
-          // value (c, k0, k1) to ob[c WE + k0 n1 + k1], then the block in
-          // contiguous pieces (the LDS operations of a wave run in order)
-          if constexpr (N0W == 1) {
-            if (cp_live) ob_lane[0] = z;
-          } else {
-            column_levels<N0W, st>(z, ring, w0, [&](auto K, float2 v) {
-              if (cp_live) ob_lane[K * N1W] = v;
-            });
-          }
-          __builtin_amdgcn_wave_barrier();
-          sfor<0, C::NR>([&](auto RR) {
-            constexpr int rr = RR;
-            const int piece = lane + 64 * rr;
-            if (rr + 1 < C::NR || piece < C::NPIECE) {
-              if constexpr (C::VEC4) {
-                const float4 v = reinterpret_cast<const float4*>(ob)[piece];
-                store_buf4<C::NT_STORES>(out, (uint32_t)(piece * 16), v);
-              } else {
-                store_buf<C::NT_STORES>(out, (uint32_t)(piece * 8), ob[piece]);
-              }
-            }
-          });
-          __builtin_amdgcn_wave_barrier();
-        } else if constexpr (N0W == 1) {
+        if constexpr (N0W == 1) {
           store_buf<C::NT_STORES>(out, lane_off, z);
         } else {
-          column_levels<N0W, st>(z, ring, w0, [&](auto K, float2 v) {
+          constexpr int t0 = T0BASE < 0 ? -1 : T0BASE + st;
+          column_levels<N0W, st, t0>(z, ring, w0, [&](auto K, float2 v) {
             store_buf<C::NT_STORES>(out, lane_off + K * N1W * (int)sizeof(float2), v);
           });
         }
       });
+    };
+    // the first periods of the slab's first chunk, which hold its priming
+    // steps, are unrolled once more with their row index known
+    constexpr int kPrimePeriods0 = (N0W - 1 + C::PERIOD - 1) / C::PERIOD;
+    constexpr int kPrimePeriods =
+        kPrimePeriods0 < C::CR / C::PERIOD ? kPrimePeriods0 : C::CR / C::PERIOD;
+    int sc0 = 0;
+    if (c == 0) {
+      sfor<0, kPrimePeriods>([&](auto SC) {
+        period(SC, std::integral_constant<int, SC * C::PERIOD>{});
+      });
+      sc0 = kPrimePeriods;
     }
+#pragma clang loop unroll(disable)
+    for (int sc = sc0; sc < C::CR / C::PERIOD; ++sc) period(sc, std::integral_constant<int, -1>{});
     __syncthreads();
     if (c + 1 < nchunks) {
       row_phase();
