@@ -107,7 +107,7 @@ __device__ __forceinline__ void tree3_fwd_tile(const void* __restrict__ xv, floa
   // inputs of this lane's passes of one chunk (planes crow + pa * RA + ra),
   // loaded a chunk ahead; planes past the volume read zero
   XT xin[C::PA][N2W];
-  auto load_chunk = [&](int64_t crow) {
+  auto load_chunk = [&](int64_t crow) __attribute__((always_inline)) {
     sfor<0, C::PA>([&](auto P) {
       constexpr int pa = P;
       const int64_t p0 = crow + pa * C::RA + pa_r;
@@ -198,7 +198,7 @@ __device__ __forceinline__ void tree3_fwd_tile(const void* __restrict__ xv, floa
     // In the slab's first chunk step st is the slab's row st: its priming
     // steps (st < n0 - 1) compute only the axis-0 levels the slab's windows
     // use (column_levels, as in the 2D kernel).
-    auto run_steps = [&](auto FIRST) {
+    auto run_steps = [&](auto FIRST) __attribute__((always_inline)) {
       sfor<0, C::CR>([&](auto STc) {
         constexpr int st = STc;
         const float2 z = zcol[st * C::ZROW];

@@ -417,12 +417,12 @@ __device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float
   // up to n1 = 32; the 64 of n1 = 64 are recomputed at each load.
   constexpr bool kKeepOffsets = N1W <= 32;
   uint32_t x_off_keep[kKeepOffsets ? N1W : 1];
-  auto x_off_of = [&](int d) -> uint32_t {
+  auto x_off_of = [&](int d) __attribute__((always_inline)) -> uint32_t {
     const int64_t col = rp_q1 + (N1W - 1 - d);
     return col < g.N1 ? (uint32_t)(((int64_t)rp_r * g.N1 + col) * EB) : kOutOfRange;
   };
   if constexpr (kKeepOffsets) sfor<0, N1W>([&](auto D) { x_off_keep[D] = x_off_of(D); });
-  auto x_off = [&](auto D) -> uint32_t {
+  auto x_off = [&](auto D) __attribute__((always_inline)) -> uint32_t {
     if constexpr (kKeepOffsets) {
       return x_off_keep[D];
     } else {
@@ -438,10 +438,13 @@ __device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float
   constexpr bool kPrefetch = N1W <= 32;
   constexpr int PASSES = C::PPW;
   XT xin[PASSES][N1W];
-  auto load_chunk = [&](int64_t crow) {
-    const int64_t rows = min((int64_t)C::CR, g.N0 - crow);
-    const auto rs = buf_rsrc(ximg + (rows > 0 ? crow : 0) * g.N1,
-                             rows > 0 ? (uint32_t)(rows * g.N1 * EB) : 0u);
+  auto load_chunk = [&](int64_t crow) __attribute__((always_inline)) {
+    // scalar values, so that the loads need no loop over distinct
+    // resources (the device min template goes through double precision)
+    const int64_t rows = clamp_i64(g.N0 - crow, 0, C::CR);
+    const auto rs = buf_rsrc(
+        (const void*)(uintptr_t)uniform_u64((uint64_t)(uintptr_t)(ximg + (rows > 0 ? crow : 0) * g.N1)),
+        uniform_u32((uint32_t)(rows * g.N1 * EB)));
     const uint32_t wave_off = (uint32_t)(wv * C::PPW * C::R * g.N1 * EB);
     sfor<0, PASSES>([&](auto PS) {
       constexpr int ps = PS;
@@ -493,7 +496,7 @@ __device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float
 
   // ---- row phase: the CR rows x QW window columns of Z of one chunk, from
   // the raw inputs in xin, into LDS
-  auto row_phase = [&]() {
+  auto row_phase = [&]() __attribute__((always_inline)) {
     sfor<0, PASSES>([&](auto PS) {
       constexpr int ps = PS;
       float2 v[N1W];
@@ -521,7 +524,11 @@ __device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float
   load_chunk(row0);
   row_phase();
   __syncthreads();
-  for (int c = 0; c < nchunks; ++c) {
+  // One chunk: c, and FIRST for the slab's first chunk, whose step st is the
+  // slab's row st and whose priming steps (st < n0 - 1) compute only the
+  // column levels that a window of the slab uses (column_levels). The first
+  // chunk is peeled off the loop, so the loop holds one copy of the steps.
+  auto chunk = [&](int c, auto FIRST) __attribute__((always_inline)) {
     const int64_t crow = row0 + (int64_t)c * C::CR;
     // (the loads of a chunk past the image bottom read zeros and touch no
     // memory; none is issued after the slab's last chunk, whose wave would
@@ -553,53 +560,37 @@ __device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float
     constexpr bool kSkip = C::CR >= 32;
     constexpr int SB = kSkip ? 8 : C::CR;
     const int live = kSkip ? min(C::CR, nrows - c * C::CR) : C::CR;
-    // Blocks [BLO, BHI) of SB steps. In the slab's first chunk (FIRST) step
-    // st is the slab's row st, and its priming steps (st < n0 - 1) compute
-    // only the column levels that a window of the slab uses (column_levels).
-    auto run_blocks = [&](auto FIRST, auto BLO, auto BHI) {
-      sfor<BLO, BHI>([&](auto BLK) {
-        if (!kSkip || BLK * SB < live) {
-          sfor<0, SB>([&](auto SS) {
-            constexpr int st = BLK * SB + SS;
-            if constexpr (st + kLdsAhead < C::CR)
-              zq[st + kLdsAhead] = zcol[(st + kLdsAhead) * C::ZROW];
-            __builtin_amdgcn_sched_barrier(0);  // keep the read ahead of this step's work
-            const float2 z = zq[st];
-            const auto out = step_rsrc(row_addr, st, sp, strip_bytes);
-            row_addr += row_bytes;
-            if constexpr (N0W == 1) {
-              store_buf<C::NT_STORES>(out, lane_off, z);
-            } else {
-              column_levels<N0W, C::KT, st % C::RING, (FIRST ? st : -1)>(
-                  z, ring, lanefac, lw, w0, [&](auto J, float2 v) {
-                    store_buf<C::NT_STORES>(
-                        out, lane_off + (C::KT * J) * N1W * (int)sizeof(float2), v);
-                  });
-            }
-          });
-        }
-      });
-    };
-    // the blocks that hold priming steps run in two versions
-    constexpr int NB = C::CR / SB;
-    constexpr int PB0 = (N0W - 1 + SB - 1) / SB;
-    constexpr int PB = PB0 < NB ? PB0 : NB;
-    using B0 = std::integral_constant<int, 0>;
-    using BP = std::integral_constant<int, PB>;
-    using BN = std::integral_constant<int, NB>;
-    if (c == 0) {
-      run_blocks(std::true_type{}, B0{}, BP{});
-    } else {
-      run_blocks(std::false_type{}, B0{}, BP{});
-    }
-    run_blocks(std::false_type{}, BP{}, BN{});
+    sfor<0, C::CR / SB>([&](auto BLK) {
+      if (!kSkip || BLK * SB < live) {
+        sfor<0, SB>([&](auto SS) {
+          constexpr int st = BLK * SB + SS;
+          if constexpr (st + kLdsAhead < C::CR)
+            zq[st + kLdsAhead] = zcol[(st + kLdsAhead) * C::ZROW];
+          __builtin_amdgcn_sched_barrier(0);  // keep the read ahead of this step's work
+          const float2 z = zq[st];
+          const auto out = step_rsrc(row_addr, st, sp, strip_bytes);
+          row_addr += row_bytes;
+          if constexpr (N0W == 1) {
+            store_buf<C::NT_STORES>(out, lane_off, z);
+          } else {
+            column_levels<N0W, C::KT, st % C::RING, (FIRST ? st : -1)>(
+                z, ring, lanefac, lw, w0, [&](auto J, float2 v) {
+                  store_buf<C::NT_STORES>(
+                      out, lane_off + (C::KT * J) * N1W * (int)sizeof(float2), v);
+                });
+          }
+        });
+      }
+    });
     __syncthreads();
     if (c + 1 < nchunks) {
       if constexpr (!kPrefetch) load_chunk(crow + C::CR);
       row_phase();
       __syncthreads();
     }
-  }
+  };
+  chunk(0, std::true_type{});
+  for (int c = 1; c < nchunks; ++c) chunk(c, std::false_type{});
 }
 
 template <int N0W, int N1W, bool REAL, int KG, int WV>

@@ -282,10 +282,13 @@ __global__ __launch_bounds__(64) void tree_mixed_kernel(const void* __restrict__
                                        : kOutOfRange;
   });
   XT xin[C::PPW][N1W];
-  auto load_chunk = [&](int64_t crow) {
-    const int64_t rows = min((int64_t)C::CR, g.N0 - crow);
-    const auto rs = buf_rsrc(ximg + (rows > 0 ? crow : 0) * g.N1,
-                             rows > 0 ? (uint32_t)(rows * g.N1 * EB) : 0u);
+  auto load_chunk = [&](int64_t crow) __attribute__((always_inline)) {
+    // scalar values, so that the loads need no loop over distinct
+    // resources (the device min template goes through double precision)
+    const int64_t rows = tree::clamp_i64(g.N0 - crow, 0, C::CR);
+    const auto rs = buf_rsrc(
+        (const void*)(uintptr_t)tree::uniform_u64((uint64_t)(uintptr_t)(ximg + (rows > 0 ? crow : 0) * g.N1)),
+        tree::uniform_u32((uint32_t)(rows * g.N1 * EB)));
     sfor<0, C::PPW>([&](auto PS) {
       constexpr int ps = PS;
       sfor<0, N1W>([&](auto D) {
@@ -310,7 +313,7 @@ __global__ __launch_bounds__(64) void tree_mixed_kernel(const void* __restrict__
   float2 ring[Radix<N0W>::RING_TOTAL];
   sfor<0, Radix<N0W>::RING_TOTAL>([&](auto K) { ring[K] = make_float2(0.f, 0.f); });
 
-  auto row_phase = [&]() {
+  auto row_phase = [&]() __attribute__((always_inline)) {
     sfor<0, C::PPW>([&](auto PS) {
       constexpr int ps = PS;
       float2 v[N1W];
@@ -348,7 +351,7 @@ __global__ __launch_bounds__(64) void tree_mixed_kernel(const void* __restrict__
     // step `row` of period sc; T0 >= 0 (the slab's first chunk, whose row
     // `row` is the slab's row `row`) lets the priming steps skip the levels
     // no window of the slab uses
-    auto period = [&](int sc, auto T0BASE) {
+    auto period = [&](int sc, auto T0BASE) __attribute__((always_inline)) {
       sfor<0, C::PERIOD>([&](auto STc) {
         constexpr int st = STc;
         const int row = sc * C::PERIOD + st;

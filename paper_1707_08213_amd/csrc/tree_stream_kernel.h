@@ -125,7 +125,7 @@ __global__ __launch_bounds__(64) void tree_stream_kernel(const void* __restrict_
   });
   constexpr int PASSES = C::CR / C::R;
   XT xin[PASSES][N1W];
-  auto load_chunk = [&](int64_t rel_c) {
+  auto load_chunk = [&](int64_t rel_c) __attribute__((always_inline)) {
     const int64_t rows = min((int64_t)C::CR, R - rel_c);
     const auto rs = buf_rsrc(x + (rows > 0 ? rel_c : 0) * sg.N1,
                              rows > 0 ? (uint32_t)(rows * sg.N1 * EB) : 0u);
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(64) void tree_stream_kernel(const void* __restrict_
     });
   };
   // ---- row phase: CR rows x QW window columns of Z into LDS
-  auto row_phase = [&]() {
+  auto row_phase = [&]() __attribute__((always_inline)) {
     sfor<0, PASSES>([&](auto PS) {
       constexpr int ps = PS;
       float2 v[N1W];
