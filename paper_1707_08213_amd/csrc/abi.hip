@@ -222,7 +222,12 @@ swdft::DenseGeom dense_geom(const swdft2d_plan_s* p) {
     if (env) S = std::atoll(env);
   }
   if (S <= 0) {
-    S = ceil_div(p->P0 * g.nstrips * p->batch, 4096);
+    // about 1024 tiles for windows of 256 values and up, 4096 below (sweep of
+    // 512-4096 tiles on gfx950: 2048x512 / 32x8 437 -> 371 us, 1024^2 /
+    // 16x16 394 -> 331 us, 8x32 423 -> 398 us, 512^2 / 16x16 102 -> 86 us;
+    // 1024^2 / 8x8 111 -> 156 us, so small windows keep the 4096)
+    const int64_t tiles = (int64_t)p->n0 * p->n1 >= 256 ? 1024 : 4096;
+    S = ceil_div(p->P0 * g.nstrips * p->batch, tiles);
     S = std::max<int64_t>(S, 64);
   }
   S = ceil_div(std::max<int64_t>(S, 16), 16) * 16;
