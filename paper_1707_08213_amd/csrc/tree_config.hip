@@ -156,6 +156,15 @@ TreeCap tree_cap(const swdft2d_plan_s* p, int kg) {
         if (columns * s <= ncu && columns * s * 10 >= ncu * 9) return TreeCap{2, s};
     } else {
       wpc = capped_by_default(p->n0, p->n1, kg) ? 1 : 2;
+      // 16 x 16 windows whose whole columns need more than one round of
+      // resident waves: slabs of about 48 rows instead, in dispatch order, so
+      // that each round of waves writes one band of rows and the last round
+      // is short (the priming rows of a slab cost little); measured against
+      // whole columns: 16 x 256^2 349 -> 321 us, 2 x 1024^2 706 -> 656 us,
+      // 2048^2 1516 -> 1373 us, 4 x 512^2 348 -> 326 us (32 or 64 rows were
+      // slower; 16 x 32 windows keep their rule)
+      if (p->n0 == 16 && p->n1 == 16 && kg == 1 && columns > ncu)
+        return TreeCap{1, std::max<int64_t>(1, ceil_div(p->P0, 48))};
     }
     if (wpc > 0) {
       const int64_t s = filling_slabs(columns, ncu * wpc);
