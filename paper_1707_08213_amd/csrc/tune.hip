@@ -6,8 +6,9 @@
 // slab lengths from a whole column down to about 4096 tiles, resident
 // workgroups per CU uncapped, 1 or 2, and one or two waves per strip; and
 // (where the shape allows and the plan's
-// algorithm is AUTO or DENSE) the dense matrix-core variant with two slab
-// lengths. The dense variant is admitted only if its output agrees with the
+// algorithm is AUTO or DENSE) the dense matrix-core variant with its
+// automatic slab and slabs of 64 to 512 window rows (fewer, longer walks are
+// often faster: their store streams interleave less). The dense variant is admitted only if its output agrees with the
 // tree's to a normwise relative difference of 1e-5 on the first
 // min(output, 8 MiB) bytes (the tree itself is within ~2e-7 of the exact
 // transform). Batched plans are tuned class by class on their own work items.
@@ -187,7 +188,7 @@ swdft_status_t tune_single(swdft2d_plan_s* p, const void* x, void* y, hipStream_
     }
   }
   if (allow_dense)
-    for (int s : {64, 128}) cands.push_back({true, 1, s, 0.f});
+    for (int s : {0, 64, 128, 256, 512}) cands.push_back({true, 1, s, 0.f});  // 0: automatic
   auto apply = [&](const Candidate& c) {
     *p = saved;
     p->tuned = true;
@@ -273,7 +274,7 @@ swdft_status_t tune_batched(swdft2d_plan_s* p, const void* x, void* y, hipStream
       for (int s : {d / 2, d, 2 * d}) cands.push_back({false, batched_tree_kg(n0, n1), s, 0.f});
     }
     if (allow_dense)
-      for (int s : {64, 128}) cands.push_back({true, 1, s, 0.f});
+      for (int s : {64, 128, 256, 512}) cands.push_back({true, 1, s, 0.f});
     auto apply = [&](const Candidate& c) -> swdft_status_t {
       bs->cfg[key] = ClassCfg{c.dense, c.slab};
       bs->tables_dirty = true;
