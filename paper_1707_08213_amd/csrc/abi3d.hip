@@ -43,26 +43,30 @@ int64_t tree3_tiles(const swdft3d_plan_s* p, int64_t S) {
   return p->batch * ceil_div(p->P0, S) * p->P1 * nstrips;
 }
 
-// Resident workgroups per CU. Capped launches whose waves each take a whole
-// column of windows (S = P0) keep the output stream in few bands of rows and
+// Resident workgroups per CU. Capped launches in dispatch order keep the
+// output stream in few bands of rows: with whole columns of windows they
 // raised the write rate of 128^3 / 8x8x8 from 5.4 to 6.1 TB/s and of
-// 96x96x192 / 4x4x4 from 4.9 to 5.4-5.9 TB/s (measured on gfx950); short
-// windows along axis 0 need more waves in flight.
+// 96x96x192 / 4x4x4 from 4.9 to 5.4-5.9 TB/s against uncapped launches
+// (measured on gfx950); short windows along axis 0 need more waves in flight.
 int32_t tree3_wpc(const swdft3d_plan_s* p) {
   const int wpc = env_int("SWDFT3D_WPC", -1);
   if (wpc >= 0) return std::min(wpc, 8);
   return p->n0 <= 4 ? 4 : 2;
 }
 
-// Window rows (axis 0) per wave: a whole column when the launch is capped;
-// otherwise enough tiles (about 4096) to fill the chip several times over,
-// with slabs long enough that the n0-1 priming rows at the top of each stay a
-// small fraction of the work. A multiple of the rows per chunk, so every chunk
-// starts on a ring period.
+// Window rows (axis 0) per wave when the launch is capped: slabs of 32 rows
+// for n0 >= 4 (the n0-1 priming rows at a slab top compute only the levels
+// its windows use, so they cost little), a whole column for n0 = 2; measured
+// at 128^3 against whole columns: 8x2x8 344 -> 318 us, 8x4x8 668 -> 634 us,
+// 4x4x4 179 -> 172 us, 8x8x8 1229 -> 1186 us, 16x4x4 673 -> 659 us, and
+// 2x8x8 344 -> 423 us. Uncapped: enough tiles (about 4096) to fill the chip
+// several times over, with slabs long enough that the priming rows stay a
+// small fraction of the work. A multiple of the rows per chunk, so every
+// chunk starts on a ring period.
 int32_t tree3_slab(const swdft3d_plan_s* p, int wpc) {
   const int cr = tree3_rows_per_chunk(p->n0, p->n1, p->n2);
   int64_t S = env_int("SWDFT3D_SLAB", 0);
-  if (S <= 0 && wpc > 0) S = p->P0;
+  if (S <= 0 && wpc > 0) S = p->n0 >= 4 ? 32 : p->P0;
   if (S <= 0) {
     const int64_t columns = tree3_tiles(p, p->P0);  // tiles with one slab
     S = ceil_div(p->P0 * columns, 4096);
