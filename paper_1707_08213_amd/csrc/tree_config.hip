@@ -171,6 +171,13 @@ TreeCap tree_cap(const swdft2d_plan_s* p, int kg) {
       if (p->n1 == 8 && ((p->n0 >= 16 && p->n0 <= 32 && kg == 2) || p->n0 == 64) &&
           columns > ncu)
         return TreeCap{1, std::max<int64_t>(1, ceil_div(p->P0, 64))};
+      // short windows with rows of 8 to 32 values: two per CU in 64-row slabs
+      // rather than the fewest slabs that fill the rounds (1024^2: 8 x 8 98
+      // -> 86 us, 8 x 16 198 -> 169 us, 4 x 8 61 -> 57 us, 4 x 16 105 -> 94
+      // us, 8 x 32 375 -> 360 us; 4 x 32 is 187 -> 194 us and n1 = 4 gains
+      // nothing, so both keep the fewest slabs)
+      if ((p->n0 == 8 && p->n1 >= 8 && p->n1 <= 32) || (p->n0 == 4 && (p->n1 == 8 || p->n1 == 16)))
+        return TreeCap{2, std::max<int64_t>(1, ceil_div(p->P0, 64))};
     }
     if (wpc > 0) {
       const int64_t s = filling_slabs(columns, ncu * wpc);
