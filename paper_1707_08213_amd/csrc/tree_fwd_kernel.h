@@ -568,6 +568,11 @@ __device__ __forceinline__ void tree_fwd_tile(const void* __restrict__ xv, float
             zq[st + kLdsAhead] = zcol[(st + kLdsAhead) * C::ZROW];
           __builtin_amdgcn_sched_barrier(0);  // keep the read ahead of this step's work
           const float2 z = zq[st];
+          // A priming step of the first chunk may only keep z in a ring for
+          // the next chunk; the compiler may then sink its LDS read past the
+          // barrier below, where another wave's row phase already overwrites
+          // the row. Taking z here as an operand keeps the read in its step.
+          if constexpr (FIRST && WV > 1) asm volatile("" ::"v"(z.x), "v"(z.y));
           const auto out = step_rsrc(row_addr, st, sp, strip_bytes);
           row_addr += row_bytes;
           if constexpr (N0W == 1) {

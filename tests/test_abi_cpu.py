@@ -380,6 +380,23 @@ def test_tree_slab_rule(N, n, slab, slabs):
     lib.swdft2d_destroy(h)
 
 
+@pytest.mark.parametrize("n0,n1,slab,slabs", [
+    (8, 8, 64, 16), (8, 16, 64, 16), (8, 32, 64, 16), (4, 8, 64, 16), (4, 16, 64, 16),
+    (4, 32, 1024, 1),   # measured slower in 64-row slabs: keeps the fewest slabs
+    (4, 4, 128, 8),     # n1 = 4: the fewest slabs that fill the rounds
+])
+def test_tree_short_window_slab_rule(n0, n1, slab, slabs):
+    """1024 x 1024 short windows: 8 x 8..32, 4 x 8 and 4 x 16 take 64-row
+    slabs (two workgroups per CU on a device); 4 x 32 and n1 = 4 do not."""
+    st, h = make_plan(1024, 1024, n0, n1)
+    assert st == 0
+    buf = ctypes.create_string_buffer(512)
+    assert lib.swdft2d_describe(h, buf, 512) == 0
+    d = buf.value.decode()
+    assert f" slab={slab} " in d and f" slabs={slabs} " in d, d
+    lib.swdft2d_destroy(h)
+
+
 @pytest.mark.parametrize("n0,n1,status", [
     (12, 9, "SWDFT_OK"), (24, 24, "SWDFT_OK"), (3, 16, "SWDFT_OK"), (8, 6, "SWDFT_OK"),
     (5, 4, "SWDFT_E_NOT_POW2"), (18, 3, "SWDFT_E_NOT_POW2"), (27, 3, "SWDFT_E_NOT_POW2"),

@@ -300,7 +300,8 @@ def test_write_probe_fills_exactly(swd, offset, count):
 
 
 @pytest.mark.parametrize("n0,n1", [(8, 8), (8, 16), (32, 16), (32, 32), (4, 16), (16, 4), (64, 8),
-                                   (8, 64), (16, 8), (4, 4)], ids=lambda v: str(v))
+                                   (8, 64), (16, 8), (4, 4), (8, 32), (4, 8), (4, 32)],
+                         ids=lambda v: str(v))
 def test_default_launch_1024_sampled(swd, orc, n0, n1):
     """The default launch at 1024 x 1024 (caps of one or two workgroups per CU,
     whole streams or split, one or two waves per strip, as the plan picks):
@@ -317,6 +318,26 @@ def test_default_launch_1024_sampled(swd, orc, n0, n1):
     torch.cuda.empty_cache()
     ref = orc.swdft2d(x.astype(np.float64), n0, n1, windows=(q0, q1))
     assert rel_err(got, ref) <= TOL_F32
+
+
+@pytest.mark.parametrize("n0,n1,cplx", [(8, 16, True), (4, 8, False), (8, 32, False),
+                                        (8, 8, True), (4, 16, False)], ids=lambda v: str(v))
+def test_short_window_slabs_full(swd, orc, n0, n1, cplx):
+    """Short windows in slabs of at most about 64 rows (ceil(P0 / 64) of
+    them, two workgroups per CU) over a 200 x 400 image: every output against
+    the oracle, the last slab ragged (193 or 197 window rows in 4 slabs)."""
+    N0, N1 = 200, 400
+    x = (workloads.normal_complex((N0, N1), seed=1700 + n0 + n1) if cplx
+         else workloads.normal_real((N0, N1), seed=1700 + n0 + n1))
+    xt = torch.from_numpy(x).cuda()
+    p = swd.Plan(N0, N1, n0, n1, dtype=xt.dtype)
+    d = p.describe()
+    print(f"[case] {d}", flush=True)
+    assert " slabs=4 " in d, d
+    y = p.forward(xt.unsqueeze(0))[0].cpu().numpy()
+    ref = orc.swdft2d(x.astype(np.complex128 if cplx else np.float64), n0, n1)
+    assert y.shape == ref.shape
+    assert rel_err(y, ref) <= TOL_F32
 
 
 @pytest.mark.parametrize("n", [4, 8, 16, 32, 64])
