@@ -152,7 +152,7 @@ def test_tune_single(swd, orc, tmp_path, monkeypatch):
 
 def test_uneven64_sampled(swd, orc):
     """64 real FP32 images, sides from {128,256,512,1024}, windows from
-    {8x8, 16x16, 32x32, 8x32}: one batched exec, 64 sampled windows per image
+    {8x8, 16x16, 32x32, 8x32}: one batched exec, 256 sampled windows per image
     (corners and edges included) against the oracle."""
     imgs = workloads.uneven64()
     shapes = [(im["x"].shape[0], im["x"].shape[1], im["n0"], im["n1"]) for im in imgs]
@@ -164,7 +164,7 @@ def test_uneven64_sampled(swd, orc):
     worst = 0.0
     for i, (im, s, o) in enumerate(zip(imgs, shapes, plan.unpack(y))):
         P0, P1 = s[0] - s[2] + 1, s[1] - s[3] + 1
-        q0, q1 = workloads.window_sample(P0, P1, 64, 4000 + i)
+        q0, q1 = workloads.window_sample(P0, P1, 256, 4000 + i)
         got = o[torch.from_numpy(q0).cuda(), torch.from_numpy(q1).cuda()].cpu().numpy()
         ref = orc.swdft2d(im["x"].astype(np.float64), s[2], s[3], windows=(q0, q1))
         e = rel_err(got, ref)
