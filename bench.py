@@ -415,8 +415,11 @@ def run_cplx2048(args, swd, dev) -> dict:
     torch.cuda.synchronize()
     d_ms, d_wall, _ = time_launches(lambda: pd.forward(x, out=y), args.steps, stream)
     got_d = sampled(y[0], q0, q1)
-    # real flops of the three split products: 8 n0 n1 (n0 + n1) per window, times 3
-    d_flops = 3 * 8 * n0 * n1 * (n0 + n1) * P0 * P1
+    # real flops of the three split products, times 3: per window position, the
+    # row product of its one new input row (n1 x n1; the n0 windows that read
+    # a row share it) and the n0 x n0 column product over n1 columns,
+    # 8 n1 (n1 + n0^2) (priming rows of a slab not counted)
+    d_flops = 3 * 8 * n1 * (n1 + n0 * n0) * P0 * P1
     dense = {"algo": "dense_bf16x2", "value": coeffs / (d_wall / args.steps), "unit": "coeffs/s",
              "avg_launch_us": d_ms * 1e3,
              "roofline": roofline(alg_bytes, d_ms, "dense_fwd_kernel<32,8,complex>"),
