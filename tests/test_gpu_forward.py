@@ -320,6 +320,38 @@ def test_default_launch_1024_sampled(swd, orc, n0, n1):
     assert rel_err(got, ref) <= TOL_F32
 
 
+@pytest.mark.parametrize("n0,n1,kg,wv,cplx", [
+    (8, 1, 2, 2, False), (16, 1, 1, 2, False), (16, 1, 2, 2, True), (16, 2, 1, 2, False),
+    (32, 1, 2, 2, False), (32, 1, 2, 2, True), (32, 2, 1, 2, True), (32, 2, 2, 2, False)],
+    ids=lambda v: str(v))
+def test_two_wave_first_chunk_repeatable(swd, orc, monkeypatch, n0, n1, kg, wv, cplx):
+    """Two waves per strip share a chunk's row levels in LDS; with slabs of
+    one or two rows every tile is mostly its first chunk, whose priming steps
+    keep row values for the next chunk. Six launches must agree bitwise, and
+    with the oracle (a read of a row after the other wave rewrote it would
+    make them differ from run to run)."""
+    monkeypatch.setenv("SWDFT_TREE_KG", str(kg))
+    monkeypatch.setenv("SWDFT_TREE_WV", str(wv))
+    N0, N1 = 3 * n0 + 37, 2 * (64 // n1) + n1 + 5
+    x = (workloads.normal_complex((N0, N1), seed=1800 + n0 + n1) if cplx
+         else workloads.normal_real((N0, N1), seed=1800 + n0 + n1))
+    xt = torch.from_numpy(x).cuda()
+    p = swd.Plan(N0, N1, n0, n1, dtype=xt.dtype)
+    d = p.describe()
+    print(f"[case] {d}", flush=True)
+    assert f" kg={kg} " in d and f" waves_per_strip={wv} " in d, d
+    y = torch.empty(p.out_shape, dtype=torch.complex64, device="cuda")
+    runs = []
+    for _ in range(6):
+        y.fill_(float("nan"))
+        p.forward(xt.unsqueeze(0), out=y)
+        runs.append(y[0].cpu().numpy().copy())
+    for r in runs[1:]:
+        assert np.array_equal(r, runs[0])
+    ref = orc.swdft2d(x.astype(np.complex128 if cplx else np.float64), n0, n1)
+    assert rel_err(runs[0], ref) <= TOL_F32
+
+
 @pytest.mark.parametrize("n0,n1,cplx", [(8, 16, True), (4, 8, False), (8, 32, False),
                                         (8, 8, True), (4, 16, False)], ids=lambda v: str(v))
 def test_short_window_slabs_full(swd, orc, n0, n1, cplx):
