@@ -397,6 +397,40 @@ def test_tree_short_window_slab_rule(n0, n1, slab, slabs):
     lib.swdft2d_destroy(h)
 
 
+@pytest.mark.parametrize("N0,N1,n0,n1,dtype,batch,slab,slabs", [
+    (1024, 1024, 16, 16, _lib.SWDFT_R32, 1, 1024, 1),   # one round of whole columns
+    (1024, 1024, 16, 16, _lib.SWDFT_R32, 2, 48, 22),    # more rounds: 48-row slabs
+    (256, 256, 16, 16, _lib.SWDFT_R32, 16, 48, 6),
+    (2048, 2048, 16, 8, _lib.SWDFT_R32, 1, 64, 32),     # two-wave n1 = 8: 64-row slabs
+    (2048, 2048, 32, 8, _lib.SWDFT_C32, 1, 64, 32),
+    (1024, 1024, 64, 8, _lib.SWDFT_R32, 1, 128, 8),     # 64 rows rounded to a whole chunk
+    (2048, 512, 32, 8, _lib.SWDFT_C32, 1, 1024, 2),     # one round: whole columns
+])
+def test_tree_multi_round_slab_rules(N0, N1, n0, n1, dtype, batch, slab, slabs):
+    """Launches whose whole columns need more than one round of resident
+    waves take short slabs (about 48 rows for 16 x 16, 64 for the two-wave
+    n1 = 8 shapes, rounded up to whole chunks); one round keeps whole
+    columns (256 compute units assumed without a device)."""
+    st, h = make_plan(N0, N1, n0, n1, dtype, batch)
+    assert st == 0
+    buf = ctypes.create_string_buffer(512)
+    assert lib.swdft2d_describe(h, buf, 512) == 0
+    d = buf.value.decode()
+    assert f" slab={slab} " in d and f" slabs={slabs} " in d, d
+    lib.swdft2d_destroy(h)
+
+
+def test_tree3d_slab_rule():
+    """128^3 / 8 x 8 x 8: 32-row slabs at the resident cap."""
+    st, h = make_plan3((128, 128, 128), (8, 8, 8))
+    assert st == 0
+    buf = ctypes.create_string_buffer(512)
+    assert lib.swdft3d_describe(h, buf, 512) == 0
+    d = buf.value.decode()
+    assert " slab=32 " in d and " slabs=4 " in d, d
+    lib.swdft3d_destroy(h)
+
+
 @pytest.mark.parametrize("n0,n1,status", [
     (12, 9, "SWDFT_OK"), (24, 24, "SWDFT_OK"), (3, 16, "SWDFT_OK"), (8, 6, "SWDFT_OK"),
     (5, 4, "SWDFT_E_NOT_POW2"), (18, 3, "SWDFT_E_NOT_POW2"), (27, 3, "SWDFT_E_NOT_POW2"),
